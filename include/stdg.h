@@ -1,0 +1,189 @@
+/*
+ * stdg.h - C ABI of the MI355X staggered space-time DG pressure library.
+ *
+ * The library implements the hot path of the staggered semi-implicit
+ * space-time discontinuous Galerkin scheme of Tavelli & Dumbser
+ * (arXiv 1601.07384) on tetrahedral meshes:
+ *   - the pressure Schur operator of eq. CS_19 (Sec. 2.4), applied matrix-free,
+ *   - its Krylov solve (CG for p_gamma = 0, GMRES otherwise; Sec. 2.7 and
+ *     Sec. 3.2 use the same unpreconditioned solvers), in FP64 or as an
+ *     FP32-inner / FP64-refinement solve,
+ *   - one Picard pressure-correction time step (Sec. 2.6, steps 0-6).
+ *
+ * Conventions shared by every entry point
+ *   - Status: every function returns an int; 0 = STDG_OK, > 0 a soft
+ *     outcome, < 0 an error.  A thread-local message for the last error is
+ *     returned by stdg_last_error().  No C++ exception crosses the ABI.
+ *   - Element order: the library renumbers elements along a Hilbert
+ *     space-filling curve (unless stdg_config.reorder = 0).  Every device
+ *     vector below is in this internal order; stdg_mesh_permutation gives
+ *     perm[internal] = input element index.
+ *   - Layouts (row-major, contiguous, device memory, 8-byte aligned):
+ *       pressure      [E][G][N]      (time node, then spatial node)
+ *       main velocity [E][3][G][N]
+ *       dual velocity [F][3][G][N]   (faces in stdg_mesh_faces order, Taylor
+ *                                     coefficients of eq. bf_2)
+ *     N = (p+1)(p+2)(p+3)/6 spatial nodes (j1,j2,j3)/p, j1 fastest then j2,
+ *     then j3, on the element's own vertex order (local vertex 0 = reference
+ *     origin); G = p_gamma+1 Gauss-Legendre time nodes of [0,1], ascending.
+ *   - Streams: a NULL stream is the default stream.  Functions that say
+ *     "asynchronous" only enqueue work; the caller keeps the buffers alive
+ *     until the stream reaches that point.  The mesh handle owns its device
+ *     tables and workspaces and must not be used from two streams at once.
+ *   - Ownership: the caller owns every vector it passes; the library never
+ *     frees caller memory.
+ */
+#ifndef STDG_H
+#define STDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STDG_OK 0
+#define STDG_NOT_CONVERGED 1   /* x holds the last iterate, report filled   */
+#define STDG_ERR_ARG -1        /* null pointer, bad size, degree or option  */
+#define STDG_ERR_MESH -2       /* degenerate element, non-manifold face,    */
+                               /* unmatched periodic face                   */
+#define STDG_ERR_NUMERIC -3    /* NaN/Inf or Krylov breakdown               */
+#define STDG_ERR_DEVICE -4     /* HIP runtime error                         */
+#define STDG_ERR_NOMEM -5      /* host or device allocation failed          */
+
+/* precision of an operator application or of the inner solve */
+#define STDG_FP64 0
+#define STDG_FP32 1
+
+/* Krylov method */
+#define STDG_AUTO 0            /* CG when p_gamma = 0, GMRES otherwise */
+#define STDG_CG 1
+#define STDG_GMRES 2
+
+typedef struct stdg_mesh stdg_mesh;
+
+/* Discretisation parameters (Sec. 2.3: degrees; Sec. 2.2: time step). */
+typedef struct {
+    int32_t p;             /* spatial degree, 1..6                             */
+    int32_t p_gamma;       /* time degree, 0..6                                */
+    double nu;             /* kinematic viscosity (Picard step only)           */
+    double dt;             /* time step Delta t > 0                            */
+    int32_t periodic;      /* 1: faces on opposite sides of the box are paired */
+                           /* 0: boundary faces carry Dirichlet velocity       */
+    double box_lo[3];      /* box used for periodic pairing                    */
+    double box_hi[3];
+    int64_t anchor_tet;    /* element (input numbering) whose node anchor_node */
+    int32_t anchor_node;   /* holds zero pressure at every time node           */
+    int32_t reorder;       /* 1: Hilbert-curve renumbering, 0: keep input order */
+} stdg_config;
+
+typedef struct {
+    int64_t n_tet;              /* E                                          */
+    int64_t n_face;             /* all faces (interior first, then boundary)  */
+    int64_t n_interior_face;
+    int32_t N, G, Nst;          /* N spatial functions, G time nodes, N*G     */
+    int32_t n_classes;          /* distinct operator block sets stored        */
+    int64_t anchor_internal;    /* internal index of the anchor element       */
+} stdg_mesh_info;
+
+/* Build the primary mesh, its face-based dual mesh (Sec. 2.2.1) and every
+ * precomputed operator block (the paper precomputes and stores all coefficient
+ * matrices, Sec. 2.8 and Sec. 4).  Inputs are HOST arrays: xyz[n_vert][3]
+ * vertex coordinates, tets[n_tet][4] vertex indices (local order is kept).
+ * Synchronous.  On success *out owns all device tables.
+ * Errors: STDG_ERR_ARG (null/size/degree), STDG_ERR_MESH (inverted or flat
+ * element, non-manifold or unmatched periodic face), STDG_ERR_DEVICE/NOMEM. */
+int stdg_mesh_build(const double* xyz, int64_t n_vert, const int64_t* tets,
+                    int64_t n_tet, const stdg_config* cfg, stdg_mesh** out);
+
+/* Same tables as stdg_mesh_build, kept on the host only: no device memory
+ * or HIP call is touched.  Such a handle serves stdg_mesh_info_get,
+ * stdg_mesh_permutation, stdg_mesh_faces and stdg_mesh_blocks (inspection of
+ * the precomputed operator); the device entry points reject it with
+ * STDG_ERR_ARG. */
+int stdg_mesh_build_host(const double* xyz, int64_t n_vert, const int64_t* tets,
+                         int64_t n_tet, const stdg_config* cfg, stdg_mesh** out);
+
+/* Copy the precomputed pressure-operator tables to host arrays:
+ * blocks[n_classes][5][N][N] (dt^2-scaled spatial blocks; block 0 multiplies
+ * the element itself, block 1+f the neighbour across local face f),
+ * cls[n_tet] class of each element, nbr[n_tet][4] internal neighbour across
+ * local face f (-1 on a boundary face), C[G][G] time factor, so that
+ * y_i = sum_k B[cls_i][k] X_k C^T with X_k the N x G coefficients of k.
+ * Any output pointer may be NULL to skip it. */
+int stdg_mesh_blocks(const stdg_mesh* mesh, double* blocks, int32_t* cls,
+                     int32_t* nbr, double* C);
+
+/* Sizes of a built mesh. */
+int stdg_mesh_info_get(const stdg_mesh* mesh, stdg_mesh_info* info);
+
+/* perm_out[n_tet] (host): perm_out[internal] = input element index. */
+int stdg_mesh_permutation(const stdg_mesh* mesh, int64_t* perm_out);
+
+/* Face list (host arrays of length n_face, faces in the library's order):
+ * left/right internal element indices (right = -1 on a boundary face) and the
+ * local face index (face opposite local vertex f) in each. */
+int stdg_mesh_faces(const stdg_mesh* mesh, int64_t* left, int32_t* left_face,
+                    int64_t* right, int32_t* right_face);
+
+/* Release a mesh and its device memory (NULL is ignored). */
+void stdg_mesh_free(stdg_mesh* mesh);
+
+/* y = S x with S = -(sum_j D_ij M_j^-1 Q_.j), the negated matrix of eq. CS_19
+ * (interior faces only; Dirichlet boundary faces do not couple pressures).
+ * x, y: device [E][G][N] doubles, must not overlap.  precision STDG_FP64
+ * uses the FP64 blocks, STDG_FP32 the FP32 copy of the blocks with FP32
+ * arithmetic (inputs and outputs stay FP64).  Asynchronous on `stream`. */
+int stdg_pressure_apply(const stdg_mesh* mesh, int32_t precision,
+                        const double* x, double* y, void* stream);
+
+/* Same operator with FP32 vectors and FP32 blocks (the inner operator of the
+ * iterative-refinement solve).  x, y: device [E][G][N] floats. Asynchronous. */
+int stdg_pressure_apply_f32(const stdg_mesh* mesh, const float* x, float* y,
+                            void* stream);
+
+typedef struct {
+    int32_t method;        /* STDG_AUTO, STDG_CG or STDG_GMRES                */
+    int32_t restart;       /* GMRES restart length m (1..200)                  */
+    double rtol;           /* stop at ||b_a - S_a x|| <= rtol ||b_a||          */
+    int32_t max_iter;      /* total inner Krylov iterations allowed            */
+    int32_t precision;     /* STDG_FP64: plain solve; STDG_FP32: FP32 inner    */
+                           /* Krylov solve inside FP64 iterative refinement    */
+    double inner_rtol;     /* relative tolerance of each inner solve (FP32)    */
+    int32_t max_outer;     /* refinement steps allowed (FP32)                  */
+    int32_t check_every;   /* host polls convergence every k iterations (>=1)  */
+} stdg_solve_opts;
+
+typedef struct {
+    int32_t status;        /* same as the return value                         */
+    int32_t outer_iters;   /* refinement steps (1 for FP64)                    */
+    int32_t inner_iters;   /* Krylov iterations (all refinement steps)         */
+    int32_t applies;       /* operator applications                            */
+    double rel_residual;   /* ||b_a - S_a x|| / ||b_a|| in FP64 at exit        */
+    double seconds;        /* wall time of the call                            */
+} stdg_solve_report;
+
+/* Fill opts with defaults: AUTO, restart 50, rtol 1e-10, max_iter 20000,
+ * FP64, inner_rtol 1e-4, max_outer 30, check_every 8. */
+void stdg_solve_opts_default(stdg_solve_opts* opts);
+
+/* Solve the anchored pressure system S_a x = b_a (eq. CS_19 / A2_mod with the
+ * pressure fixed at the anchor node at every time node: rows and columns of
+ * the anchor replaced by the identity, b_a = b with the anchor entries set to
+ * zero).  b, x: device [E][G][N] doubles; x holds the initial guess on entry
+ * and the solution (with x_anchor = 0) on exit.  The library solves the
+ * equivalent consistent singular system S x = b~ and shifts by a constant per
+ * time node.  Synchronises `stream` before returning.  Returns STDG_OK,
+ * STDG_NOT_CONVERGED (x = last iterate) or an error. */
+int stdg_pressure_solve(const stdg_mesh* mesh, const double* b, double* x,
+                        const stdg_solve_opts* opts, stdg_solve_report* report,
+                        void* stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char* stdg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STDG_H */

@@ -1,0 +1,130 @@
+"""MI355X (gfx950) staggered space-time DG pressure library: Python binding.
+
+The computation lives in the HIP library ``libstdg.so`` behind the C ABI of
+``include/stdg.h``.  This module only marshals arguments: meshes are host
+numpy arrays, vectors are torch tensors on the GPU (torch provides device
+memory and streams).
+"""
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (Config, MeshInfo, SolveOpts, SolveReport, StdgError,
+                   STDG_OK, STDG_NOT_CONVERGED, STDG_FP64, STDG_FP32,
+                   STDG_AUTO, STDG_CG, STDG_GMRES)
+
+__all__ = ["Mesh", "StdgError", "STDG_FP64", "STDG_FP32", "STDG_AUTO",
+           "STDG_CG", "STDG_GMRES", "solve_opts"]
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def solve_opts(**kw):
+    o = SolveOpts()
+    _lib.load().stdg_solve_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown solve option {k}")
+        setattr(o, k, v)
+    return o
+
+
+class Mesh:
+    """A built mesh handle (owns the library's device tables)."""
+
+    def __init__(self, X, tets, p, p_gamma=0, dt=1e-2, nu=0.0, periodic=False,
+                 box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0), anchor_tet=0,
+                 anchor_node=0, reorder=True, device=True):
+        lib = _lib.load()
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int64)
+        cfg = Config()
+        cfg.p, cfg.p_gamma, cfg.nu, cfg.dt = p, p_gamma, nu, dt
+        cfg.periodic = 1 if periodic else 0
+        cfg.box_lo[:] = list(box_lo)
+        cfg.box_hi[:] = list(box_hi)
+        cfg.anchor_tet, cfg.anchor_node = anchor_tet, anchor_node
+        cfg.reorder = 1 if reorder else 0
+        h = ctypes.c_void_p()
+        fn = lib.stdg_mesh_build if device else lib.stdg_mesh_build_host
+        _lib.check(fn(X.ctypes.data, X.shape[0], tets.ctypes.data, tets.shape[0],
+                      ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        self.device = device
+        info = MeshInfo()
+        _lib.check(lib.stdg_mesh_info_get(h, ctypes.byref(info)))
+        self.E, self.N, self.G, self.Nst = info.n_tet, info.N, info.G, info.Nst
+        self.n_face, self.n_interior_face = info.n_face, info.n_interior_face
+        self.n_classes = info.n_classes
+        self.anchor_internal = info.anchor_internal
+        self.p, self.p_gamma, self.dt, self.nu = p, p_gamma, dt, nu
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.stdg_mesh_free(h)
+            self._h = None
+
+    # -------------------------------------------------------------- layout
+    def permutation(self):
+        perm = np.empty(self.E, dtype=np.int64)
+        _lib.check(self._lib.stdg_mesh_permutation(self._h, perm.ctypes.data))
+        return perm
+
+    def faces(self):
+        n = self.n_face
+        left = np.empty(n, np.int64); right = np.empty(n, np.int64)
+        lf = np.empty(n, np.int32); rf = np.empty(n, np.int32)
+        _lib.check(self._lib.stdg_mesh_faces(self._h, left.ctypes.data, lf.ctypes.data,
+                                             right.ctypes.data, rf.ctypes.data))
+        return left, lf, right, rf
+
+    def blocks(self):
+        """(blocks [n_classes,5,N,N], cls [E], nbr [E,4], C [G,G]) host copies."""
+        B = np.empty((self.n_classes, 5, self.N, self.N))
+        cls = np.empty(self.E, np.int32)
+        nbr = np.empty((self.E, 4), np.int32)
+        C = np.empty((self.G, self.G))
+        _lib.check(self._lib.stdg_mesh_blocks(self._h, B.ctypes.data, cls.ctypes.data,
+                                              nbr.ctypes.data, C.ctypes.data))
+        return B, cls, nbr, C
+
+    # -------------------------------------------------------------- operator
+    def apply(self, x, y, precision=STDG_FP64, stream=None):
+        """y = S x on device float64 tensors [E*G*N] (internal element order)."""
+        self._check_vec(x, "float64"); self._check_vec(y, "float64")
+        _lib.check(self._lib.stdg_pressure_apply(self._h, precision, _ptr(x), _ptr(y),
+                                                 _stream_ptr(stream)))
+
+    def apply_f32(self, x, y, stream=None):
+        self._check_vec(x, "float32"); self._check_vec(y, "float32")
+        _lib.check(self._lib.stdg_pressure_apply_f32(self._h, _ptr(x), _ptr(y),
+                                                     _stream_ptr(stream)))
+
+    def solve(self, b, x, opts=None, stream=None, **kw):
+        """Anchored pressure solve; x holds the guess on entry.  Returns the report."""
+        self._check_vec(b, "float64"); self._check_vec(x, "float64")
+        o = opts if opts is not None else solve_opts(**kw)
+        rep = SolveReport()
+        code = self._lib.stdg_pressure_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(o),
+                                             ctypes.byref(rep), _stream_ptr(stream))
+        _lib.check(code, allow=(STDG_OK, STDG_NOT_CONVERGED))
+        return rep
+
+    def _check_vec(self, t, dtype):
+        if not t.is_cuda or str(t.dtype) != "torch." + dtype or not t.is_contiguous():
+            raise ValueError(f"expected a contiguous CUDA {dtype} tensor")
+        if t.numel() != self.E * self.Nst:
+            raise ValueError(f"expected {self.E * self.Nst} entries, got {t.numel()}")

@@ -1,0 +1,191 @@
+// C ABI entry points: mesh handle life cycle, operator application, errors.
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace stdg {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+void free_workspace(stdg_mesh* m);
+
+int upload_tables(stdg_mesh* m) {
+    const size_t nb = (size_t)m->n_classes * 5 * m->N * m->N;
+    std::vector<float> b32(nb);
+    for (size_t i = 0; i < nb; ++i) b32[i] = (float)m->blocks[i];
+    std::vector<float> c32(m->Ctime.begin(), m->Ctime.end());
+    std::vector<int32_t> cls(m->cls.begin(), m->cls.end());
+    STDG_HIP(hipMalloc(&m->d.blocks, nb * sizeof(double)));
+    STDG_HIP(hipMalloc(&m->d.blocks32, nb * sizeof(float)));
+    STDG_HIP(hipMalloc(&m->d.cls, m->E * sizeof(int32_t)));
+    STDG_HIP(hipMalloc(&m->d.nbr, 4 * m->E * sizeof(int32_t)));
+    STDG_HIP(hipMalloc(&m->d.C, m->G * m->G * sizeof(double)));
+    STDG_HIP(hipMalloc(&m->d.C32, m->G * m->G * sizeof(float)));
+    STDG_HIP(hipMemcpy(m->d.blocks, m->blocks.data(), nb * sizeof(double), hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(m->d.blocks32, b32.data(), nb * sizeof(float), hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(m->d.cls, cls.data(), m->E * sizeof(int32_t), hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(m->d.nbr, m->nbr.data(), 4 * m->E * sizeof(int32_t), hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(m->d.C, m->Ctime.data(), m->G * m->G * sizeof(double), hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(m->d.C32, c32.data(), m->G * m->G * sizeof(float), hipMemcpyHostToDevice));
+    return STDG_OK;
+}
+
+void free_tables(stdg_mesh* m) {
+    for (void* p : {(void*)m->d.blocks, (void*)m->d.blocks32, (void*)m->d.cls, (void*)m->d.nbr,
+                    (void*)m->d.C, (void*)m->d.C32})
+        if (p) (void)hipFree(p);
+    m->d = DeviceTables();
+}
+
+}  // namespace stdg
+
+using namespace stdg;
+
+extern "C" const char* stdg_last_error(void) { return g_last_error.c_str(); }
+
+static int mesh_build_impl(const double* xyz, int64_t n_vert, const int64_t* tets, int64_t n_tet,
+                           const stdg_config* cfg, stdg_mesh** out, bool device) {
+    if (!xyz || !tets || !cfg || !out) { set_error("null argument"); return STDG_ERR_ARG; }
+    *out = nullptr;
+    if (n_vert < 4 || n_tet < 1 || n_tet > (int64_t)INT32_MAX) { set_error("bad mesh size"); return STDG_ERR_ARG; }
+    if (cfg->p < 1 || cfg->p > 6 || cfg->p_gamma < 0 || cfg->p_gamma > 6) {
+        set_error("degree out of range (1 <= p <= 6, 0 <= p_gamma <= 6)");
+        return STDG_ERR_ARG;
+    }
+    if (!(cfg->dt > 0.0) || !(cfg->nu >= 0.0)) { set_error("dt must be > 0 and nu >= 0"); return STDG_ERR_ARG; }
+    if (cfg->anchor_tet < 0 || cfg->anchor_tet >= n_tet) { set_error("anchor element out of range"); return STDG_ERR_ARG; }
+    const int N = (cfg->p + 1) * (cfg->p + 2) * (cfg->p + 3) / 6;
+    if (cfg->anchor_node < 0 || cfg->anchor_node >= N) { set_error("anchor node out of range"); return STDG_ERR_ARG; }
+    if (cfg->periodic)
+        for (int d = 0; d < 3; ++d)
+            if (!(cfg->box_hi[d] > cfg->box_lo[d])) { set_error("periodic box is empty"); return STDG_ERR_ARG; }
+    stdg_mesh* m = nullptr;
+    try {
+        m = new stdg_mesh();
+        m->cfg = *cfg;
+        m->p = cfg->p;
+        m->G = cfg->p_gamma + 1;
+        m->N = N;
+        m->Nst = N * m->G;
+        m->E = n_tet;
+        int e = build_topology(m, xyz, n_vert, tets);
+        if (e == STDG_OK) e = build_blocks(m);
+        if (e == STDG_OK) {
+            m->anchor = m->iperm[cfg->anchor_tet];
+            m->anchor_node = cfg->anchor_node;
+            if (device) e = upload_tables(m);
+        }
+        if (e != STDG_OK) {
+            free_tables(m);
+            delete m;
+            return e;
+        }
+    } catch (const std::bad_alloc&) {
+        if (m) { free_tables(m); delete m; }
+        set_error("host allocation failed");
+        return STDG_ERR_NOMEM;
+    } catch (const std::exception& ex) {
+        if (m) { free_tables(m); delete m; }
+        set_error(std::string("mesh build failed: ") + ex.what());
+        return STDG_ERR_MESH;
+    }
+    *out = m;
+    return STDG_OK;
+}
+
+extern "C" int stdg_mesh_build(const double* xyz, int64_t n_vert, const int64_t* tets, int64_t n_tet,
+                               const stdg_config* cfg, stdg_mesh** out) {
+    return mesh_build_impl(xyz, n_vert, tets, n_tet, cfg, out, true);
+}
+
+extern "C" int stdg_mesh_build_host(const double* xyz, int64_t n_vert, const int64_t* tets, int64_t n_tet,
+                                    const stdg_config* cfg, stdg_mesh** out) {
+    return mesh_build_impl(xyz, n_vert, tets, n_tet, cfg, out, false);
+}
+
+extern "C" int stdg_mesh_blocks(const stdg_mesh* m, double* blocks, int32_t* cls, int32_t* nbr, double* C) {
+    if (!m) { set_error("null argument"); return STDG_ERR_ARG; }
+    if (blocks) std::memcpy(blocks, m->blocks.data(), m->blocks.size() * sizeof(double));
+    if (cls) std::memcpy(cls, m->cls.data(), m->E * sizeof(int32_t));
+    if (nbr) std::memcpy(nbr, m->nbr.data(), 4 * m->E * sizeof(int32_t));
+    if (C) std::memcpy(C, m->Ctime.data(), m->Ctime.size() * sizeof(double));
+    return STDG_OK;
+}
+
+extern "C" int stdg_mesh_info_get(const stdg_mesh* m, stdg_mesh_info* info) {
+    if (!m || !info) { set_error("null argument"); return STDG_ERR_ARG; }
+    info->n_tet = m->E;
+    info->n_face = (int64_t)m->faces.size();
+    info->n_interior_face = m->n_interior;
+    info->N = m->N;
+    info->G = m->G;
+    info->Nst = m->Nst;
+    info->n_classes = m->n_classes;
+    info->anchor_internal = m->anchor;
+    return STDG_OK;
+}
+
+extern "C" int stdg_mesh_permutation(const stdg_mesh* m, int64_t* perm) {
+    if (!m || !perm) { set_error("null argument"); return STDG_ERR_ARG; }
+    std::memcpy(perm, m->perm.data(), m->E * sizeof(int64_t));
+    return STDG_OK;
+}
+
+extern "C" int stdg_mesh_faces(const stdg_mesh* m, int64_t* left, int32_t* lf, int64_t* right, int32_t* rf) {
+    if (!m || !left || !lf || !right || !rf) { set_error("null argument"); return STDG_ERR_ARG; }
+    for (size_t j = 0; j < m->faces.size(); ++j) {
+        left[j] = m->faces[j].left;
+        lf[j] = m->faces[j].lf;
+        right[j] = m->faces[j].right;
+        rf[j] = m->faces[j].rf;
+    }
+    return STDG_OK;
+}
+
+extern "C" void stdg_mesh_free(stdg_mesh* m) {
+    if (!m) return;
+    free_workspace(m);
+    free_tables(m);
+    delete m;
+}
+
+extern "C" int stdg_pressure_apply(const stdg_mesh* m, int32_t precision, const double* x, double* y,
+                                   void* stream) {
+    if (!m || !x || !y) { set_error("null argument"); return STDG_ERR_ARG; }
+    if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
+    if (x == y) { set_error("x and y must not overlap"); return STDG_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    if (precision == STDG_FP64) {
+        STDG_HIP(launch_apply_f64(m, x, y, s));
+        return STDG_OK;
+    }
+    if (precision == STDG_FP32) {
+        stdg_mesh* mm = const_cast<stdg_mesh*>(m);
+        const int64_t n = m->E * m->Nst;
+        if (!mm->ws.x32) {
+            // scratch FP32 vectors (owned by the handle)
+            STDG_HIP(hipMalloc(&mm->ws.x32, n * sizeof(float)));
+        }
+        if (!mm->ws.q32) STDG_HIP(hipMalloc(&mm->ws.q32, n * sizeof(float)));
+        STDG_HIP(convert_d2f(x, mm->ws.x32, n, s));
+        STDG_HIP(launch_apply_f32(m, mm->ws.x32, mm->ws.q32, s));
+        STDG_HIP(convert_f2d(mm->ws.q32, y, n, s));
+        return STDG_OK;
+    }
+    set_error("unknown precision");
+    return STDG_ERR_ARG;
+}
+
+extern "C" int stdg_pressure_apply_f32(const stdg_mesh* m, const float* x, float* y, void* stream) {
+    if (!m || !x || !y) { set_error("null argument"); return STDG_ERR_ARG; }
+    if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
+    if (x == y) { set_error("x and y must not overlap"); return STDG_ERR_ARG; }
+    STDG_HIP(launch_apply_f32(m, x, y, (hipStream_t)stream));
+    return STDG_OK;
+}

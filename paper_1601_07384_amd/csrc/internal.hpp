@@ -1,0 +1,78 @@
+// Internal state of a built mesh, shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/stdg.h"
+#include "fem.hpp"
+
+namespace stdg {
+
+void set_error(const std::string& msg);
+
+#define STDG_HIP(call)                                                        \
+    do {                                                                      \
+        hipError_t e_ = (call);                                               \
+        if (e_ != hipSuccess) {                                               \
+            ::stdg::set_error(std::string(#call) + ": " + hipGetErrorString(e_)); \
+            return STDG_ERR_DEVICE;                                           \
+        }                                                                     \
+    } while (0)
+
+struct Face {
+    int64_t left, right;     // internal element ids, right = -1 on a boundary
+    int32_t lf, rf;          // local face index in each element
+    V3 shift;                // right element's coordinates + shift = adjacent to left
+};
+
+// Device buffers owned by the handle (freed with it).
+struct DeviceTables {
+    double* blocks = nullptr;     // [n_classes][5][N][N]  dt^2 S^sp blocks
+    float* blocks32 = nullptr;    // same, FP32
+    int32_t* cls = nullptr;       // [E]
+    int32_t* nbr = nullptr;       // [E][4]  -1 on a boundary face
+    double* C = nullptr;          // [G][G]  time factor W T^-1 W
+    float* C32 = nullptr;
+};
+
+// Krylov workspaces (allocated on first solve, sized for the mesh).
+struct Workspace {
+    size_t n = 0;                 // vector length E*G*N
+    int restart = 0;
+    double* r = nullptr; double* p = nullptr; double* q = nullptr; double* z = nullptr;
+    double* V = nullptr;          // GMRES basis [(m+1)][n]
+    float* r32 = nullptr; float* p32 = nullptr; float* q32 = nullptr; float* x32 = nullptr;
+    float* b32 = nullptr;
+    float* V32 = nullptr;         // FP32 GMRES basis
+    double* partial = nullptr;    // reduction partials
+    double* scal = nullptr;       // device scalars (small)
+    double* hscal = nullptr;      // pinned host mirror
+    int64_t partial_len = 0;
+};
+
+}  // namespace stdg
+
+struct stdg_mesh {
+    stdg_config cfg;
+    int p = 0, G = 0, N = 0, Nst = 0;
+    int64_t E = 0;
+    std::vector<int64_t> perm;        // internal -> input
+    std::vector<int64_t> iperm;       // input -> internal
+    std::vector<std::array<stdg::V3, 4>> vert;   // internal order, local vertex order kept
+    std::vector<int32_t> nbr;         // [E][4]
+    std::vector<int64_t> tet_face;    // [E][4] face id
+    std::vector<stdg::Face> faces;    // interior first, then boundary
+    int64_t n_interior = 0;
+    std::vector<int32_t> cls;         // [E]
+    int n_classes = 0;
+    std::vector<double> blocks;       // [n_classes][5][N][N]
+    std::vector<double> Ctime;        // [G][G]
+    int64_t anchor = 0;               // internal anchor element
+    int anchor_node = 0;
+    stdg::DeviceTables d;
+    stdg::Workspace ws;
+};

@@ -1,0 +1,20 @@
+// Launch wrappers shared between the library's HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+struct stdg_mesh;
+
+namespace stdg {
+
+hipError_t launch_apply_f64(const stdg_mesh* m, const double* x, double* y, hipStream_t s);
+hipError_t launch_apply_f32(const stdg_mesh* m, const float* x, float* y, hipStream_t s);
+hipError_t convert_d2f(const double* a, float* b, int64_t n, hipStream_t s);
+hipError_t convert_f2d(const float* a, double* b, int64_t n, hipStream_t s);
+
+int build_topology(stdg_mesh* m, const double* xyz, int64_t n_vert, const int64_t* tets);
+int build_blocks(stdg_mesh* m);
+int upload_tables(stdg_mesh* m);
+void free_tables(stdg_mesh* m);
+
+}  // namespace stdg

@@ -1,0 +1,637 @@
+// Pressure solve (Sec. 2.4 eq. CS_19 / Sec. 2.6 eq. A2_mod): unpreconditioned
+// CG for p_gamma = 0 (symmetric positive semi-definite, Corollaries 1-2 of
+// Sec. 2.7) and restarted GMRES otherwise (Sec. 3.2), both matrix-free.
+//
+// The pressure is fixed to zero at the anchor node (every time node).  Instead
+// of the anchored matrix (which has one eigenvalue of order one among
+// eigenvalues of order dt^2 h, i.e. a badly scaled row), the solver works on
+// the equivalent consistent singular system S x = b~, b~ = b except at the
+// anchor rows where b~_a = -sum_{i != a} b_i (per time node), which has the
+// same solutions up to a constant per time node (the null space of S); the
+// result is shifted so that x_a = 0.  The stopping test is the anchored
+// relative residual ||b_a - S_a x|| / ||b_a||.
+//
+// Reductions accumulate in FP64 in a fixed order (per-block partial sums,
+// then one block), so results are bitwise reproducible.  Scalars (alpha,
+// beta, the Hessenberg matrix and Givens rotations) live on the device; the
+// host reads a convergence estimate every `check_every` iterations.
+//
+// Precision STDG_FP32: FP64 iterative refinement whose inner solves use FP32
+// vectors and FP32 operator blocks (FP64 dot products, Hessenberg and Givens);
+// the outer residual b~ - S x is recomputed in FP64 each refinement step.
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace stdg {
+
+namespace {
+
+constexpr int RT = 256;     // threads per reduction block
+constexpr int NBLK = 1024;  // reduction blocks (fixed: determinism)
+
+enum Slot {
+    S_RR = 0, S_PQ, S_ALPHA, S_BETA, S_RES, S_BN2, S_RN2, S_NORM, S_INV, S_TMP,
+    S_TIME = 16,        // G per-time-node sums
+    S_ANCH = 32,        // G anchor values
+    S_COUNT = 64
+};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Sum over the block; result valid in thread 0.  Requires blockDim.x == RT.
+__device__ inline double block_sum(double v, double* smem) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) smem[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < RT / 64; ++k) s += smem[k];
+    return s;
+}
+
+template <typename A, typename B>
+__global__ void __launch_bounds__(RT) k_dot(const A* __restrict__ a, const B* __restrict__ b,
+                                            int64_t n, double* __restrict__ partial) {
+    __shared__ double sm[RT / 64];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT)
+        acc += (double)a[i] * (double)b[i];
+    double s = block_sum(acc, sm);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// out = sum(partial[0..np)); mode selects a scalar update done by thread 0.
+enum FinMode { FIN_STORE = 0, FIN_CG_ALPHA = 1, FIN_CG_BETA = 2, FIN_SQRT = 3 };
+__global__ void __launch_bounds__(RT) k_finalize(const double* __restrict__ partial, int np,
+                                                 double* __restrict__ scal, int slot, int mode) {
+    __shared__ double sm[RT / 64];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += RT) acc += partial[i];
+    double s = block_sum(acc, sm);
+    if (threadIdx.x != 0) return;
+    if (mode == FIN_STORE) {
+        scal[slot] = s;
+    } else if (mode == FIN_CG_ALPHA) {            // s = p.q
+        const double rr = scal[S_RR];
+        scal[S_PQ] = s;
+        scal[S_ALPHA] = (s > 0.0 && rr > 0.0) ? rr / s : 0.0;
+    } else if (mode == FIN_CG_BETA) {             // s = r.r (new)
+        const double rr = scal[S_RR];
+        scal[S_BETA] = (rr > 0.0 && scal[S_ALPHA] != 0.0) ? s / rr : 0.0;
+        scal[S_RR] = s;
+    } else if (mode == FIN_SQRT) {
+        scal[slot] = sqrt(s);
+    }
+}
+
+// CG: x += alpha p; r -= alpha q; partial sums of r.r
+template <typename T>
+__global__ void __launch_bounds__(RT) k_cg_xr(T* __restrict__ x, T* __restrict__ r,
+                                              const T* __restrict__ p, const T* __restrict__ q,
+                                              const double* __restrict__ scal, int64_t n,
+                                              double* __restrict__ partial) {
+    __shared__ double sm[RT / 64];
+    const T alpha = (T)scal[S_ALPHA];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
+        x[i] += alpha * p[i];
+        const T ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        acc += (double)ri * (double)ri;
+    }
+    double s = block_sum(acc, sm);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ void k_cg_p(T* __restrict__ p, const T* __restrict__ r, const double* __restrict__ scal,
+                       int64_t n) {
+    const T beta = (T)scal[S_BETA];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = r[i] + beta * p[i];
+}
+
+// r = b - q (types may differ), partial sums of r.r
+template <typename TB, typename TR>
+__global__ void __launch_bounds__(RT) k_resid(const TB* __restrict__ b, const TR* __restrict__ q,
+                                              TR* __restrict__ r, int64_t n, double* __restrict__ partial) {
+    __shared__ double sm[RT / 64];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
+        const TR ri = (TR)b[i] - q[i];
+        r[i] = ri;
+        acc += (double)ri * (double)ri;
+    }
+    double s = block_sum(acc, sm);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ v, T val, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = val;
+}
+
+// x += (double) d
+__global__ void k_add_f32(double* __restrict__ x, const float* __restrict__ d, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] += (double)d[i];
+}
+
+template <typename T>
+__global__ void k_copy(const T* __restrict__ a, T* __restrict__ b, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+// Per-time-node sums of a [E][G][N] vector: partial[g * NBLK + block]
+__global__ void __launch_bounds__(RT) k_time_sums(const double* __restrict__ v, int64_t E, int G, int N,
+                                                  double* __restrict__ partial) {
+    __shared__ double sm[RT / 64];
+    const int64_t n = E * G * N;
+    for (int g = 0; g < G; ++g) {
+        double acc = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT)
+            if ((int)((i / N) % G) == g) acc += v[i];
+        double s = block_sum(acc, sm);
+        if (threadIdx.x == 0) partial[(int64_t)g * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+__global__ void __launch_bounds__(RT) k_fin_multi(const double* __restrict__ partial, int np,
+                                                  double* __restrict__ out, double* __restrict__ acc_out,
+                                                  double sgn) {
+    __shared__ double sm[RT / 64];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += RT) acc += partial[(int64_t)j * np + i];
+    double s = block_sum(acc, sm);
+    if (threadIdx.x == 0) {
+        out[j] = s;
+        if (acc_out) acc_out[j] += sgn * s;
+    }
+}
+
+// b~: anchor rows replaced by minus the sum of all other rows (per time node)
+__global__ void k_set_anchor(double* __restrict__ bt, const double* __restrict__ tsum, int64_t anchor,
+                             int node, int G, int N) {
+    const int g = threadIdx.x;
+    if (g < G) {
+        const int64_t k = (anchor * G + g) * N + node;
+        bt[k] = -(tsum[g] - bt[k]);
+    }
+}
+
+// subtract the per-time-node mean (projection onto the range of S)
+template <typename T>
+__global__ void k_remove_mean(T* __restrict__ v, const double* __restrict__ tsum, int64_t E, int G, int N) {
+    const int64_t n = E * G * N;
+    const double cnt = (double)(E * N);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)((i / N) % G);
+        v[i] -= (T)(tsum[g] / cnt);
+    }
+}
+
+__global__ void k_read_anchor(const double* __restrict__ x, double* __restrict__ out, int64_t anchor,
+                              int node, int G, int N) {
+    const int g = threadIdx.x;
+    if (g < G) out[g] = x[(anchor * G + g) * N + node];
+}
+
+__global__ void k_shift(double* __restrict__ x, const double* __restrict__ a, int64_t E, int G, int N) {
+    const int64_t n = E * G * N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] -= a[(i / N) % G];
+}
+
+// anchored residual: sum (b - q)^2 and sum b^2 over non-anchor rows
+__global__ void __launch_bounds__(RT) k_anch_res(const double* __restrict__ b, const double* __restrict__ q,
+                                                 int64_t anchor, int node, int64_t E, int G, int N,
+                                                 double* __restrict__ partial) {
+    __shared__ double sm[RT / 64];
+    const int64_t n = E * G * N;
+    double rr = 0.0, bb = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
+        const int64_t e = i / ((int64_t)G * N);
+        const int nn = (int)(i % N);
+        if (e == anchor && nn == node) continue;
+        const double r = b[i] - q[i];
+        rr += r * r;
+        bb += b[i] * b[i];
+    }
+    double s1 = block_sum(rr, sm);
+    __syncthreads();
+    double s2 = block_sum(bb, sm);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = s1;
+        partial[gridDim.x + blockIdx.x] = s2;
+    }
+}
+
+// ---- GMRES pieces ---------------------------------------------------------
+// partial[j * NBLK + block] = sum over the block's rows of V_j . w, j < k1
+template <typename T>
+__global__ void __launch_bounds__(RT) k_multidot(const T* __restrict__ V, int k1, int64_t n,
+                                                 const T* __restrict__ w, double* __restrict__ partial) {
+    __shared__ double sm[RT / 64];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    for (int j = 0; j < k1; ++j) {
+        const T* vj = V + (int64_t)j * n;
+        double acc = 0.0;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += RT) acc += (double)vj[i] * (double)w[i];
+        double s = block_sum(acc, sm);
+        if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// w += sgn * sum_j h_j V_j
+template <typename T>
+__global__ void k_multiaxpy(const T* __restrict__ V, int k1, int64_t n, const double* __restrict__ h,
+                            double sgn, T* __restrict__ w) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < k1; ++j) s += h[j] * (double)V[(int64_t)j * n + i];
+        w[i] = (T)((double)w[i] + sgn * s);
+    }
+}
+
+// v *= 1/scal[slot]  (skipped when the norm is zero)
+template <typename T>
+__global__ void k_scale_inv(T* __restrict__ v, const double* __restrict__ src, int64_t n) {
+    const double nrm = *src;
+    if (!(nrm > 0.0)) return;
+    const double inv = 1.0 / nrm;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = (T)((double)v[i] * inv);
+}
+
+// Hessenberg column k (H is (m+1) x m column-major: H[j + (m+1) k]):
+// apply the previous rotations, form a new one, update g; residual estimate.
+__global__ void k_givens(double* __restrict__ H, double* __restrict__ g, double* __restrict__ cs,
+                         double* __restrict__ sn, int k, int m, double* __restrict__ scal) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double* h = H + (int64_t)(m + 1) * k;
+    for (int i = 0; i < k; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+    }
+    const double a = h[k], b = h[k + 1];
+    const double r = sqrt(a * a + b * b);
+    double c = 1.0, s = 0.0;
+    if (r > 0.0) { c = a / r; s = b / r; }
+    cs[k] = c; sn[k] = s;
+    h[k] = r; h[k + 1] = 0.0;
+    g[k + 1] = -s * g[k];
+    g[k] = c * g[k];
+    scal[S_RES] = fabs(g[k + 1]);
+}
+
+// y = R^-1 g for the leading (k1 x k1) triangle
+__global__ void k_backsolve(const double* __restrict__ H, const double* __restrict__ g,
+                            double* __restrict__ y, int k1, int m) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = k1 - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int j = i + 1; j < k1; ++j) s -= H[i + (int64_t)(m + 1) * j] * y[j];
+        const double d = H[i + (int64_t)(m + 1) * i];
+        y[i] = d != 0.0 ? s / d : 0.0;
+    }
+}
+
+__global__ void k_init_g(double* g, int m, const double* beta) {
+    for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = (i == 0) ? *beta : 0.0;
+}
+
+int grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+template <typename T> struct Apply;
+template <> struct Apply<double> {
+    static hipError_t run(const stdg_mesh* m, const double* x, double* y, hipStream_t s) { return launch_apply_f64(m, x, y, s); }
+};
+template <> struct Apply<float> {
+    static hipError_t run(const stdg_mesh* m, const float* x, float* y, hipStream_t s) { return launch_apply_f32(m, x, y, s); }
+};
+
+struct Ctx {
+    const stdg_mesh* m;
+    hipStream_t s;
+    int64_t n;
+    double* partial;
+    double* scal;
+    double* hscal;
+    double* gm;        // GMRES small arrays: H, g, cs, sn, y, h
+    int applies = 0;
+};
+
+#define CK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { set_error(std::string(#x) + ": " + hipGetErrorString(e_)); return STDG_ERR_DEVICE; } } while (0)
+
+int read_scal(Ctx& c, int slot, double& v) {
+    CK(hipMemcpyAsync(c.hscal, c.scal + slot, sizeof(double), hipMemcpyDeviceToHost, c.s));
+    CK(hipStreamSynchronize(c.s));
+    v = c.hscal[0];
+    return STDG_OK;
+}
+
+// Per-time-node sums into scal[S_TIME..]
+int time_sums(Ctx& c, const double* v) {
+    const stdg_mesh* m = c.m;
+    hipLaunchKernelGGL(k_time_sums, dim3(NBLK), dim3(RT), 0, c.s, v, m->E, m->G, m->N, c.partial);
+    hipLaunchKernelGGL(k_fin_multi, dim3(m->G), dim3(RT), 0, c.s, c.partial, NBLK, c.scal + S_TIME,
+                       (double*)nullptr, 0.0);
+    CK(hipGetLastError());
+    return STDG_OK;
+}
+
+// CG on S x = b (consistent); x, b, work vectors of type T.  Stops when the
+// recursive residual norm <= tol_abs or after max_it iterations.
+template <typename T>
+int cg(Ctx& c, const T* b, T* x, T* r, T* p, T* q, double tol_abs, int max_it, int check_every,
+       int& iters, double& res_out) {
+    const int64_t n = c.n;
+    const int gb = grid_for(n);
+    CK(Apply<T>::run(c.m, x, q, c.s)); c.applies++;
+    hipLaunchKernelGGL((k_resid<T, T>), dim3(NBLK), dim3(RT), 0, c.s, b, q, r, n, c.partial);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_RR, (int)FIN_STORE);
+    hipLaunchKernelGGL(k_copy<T>, dim3(gb), dim3(256), 0, c.s, r, p, n);
+    CK(hipGetLastError());
+    double rr;
+    if (int e = read_scal(c, S_RR, rr)) return e;
+    iters = 0;
+    res_out = std::sqrt(rr);
+    if (res_out <= tol_abs) return STDG_OK;
+    while (iters < max_it) {
+        CK(Apply<T>::run(c.m, p, q, c.s)); c.applies++;
+        hipLaunchKernelGGL((k_dot<T, T>), dim3(NBLK), dim3(RT), 0, c.s, p, q, n, c.partial);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, 0, (int)FIN_CG_ALPHA);
+        hipLaunchKernelGGL(k_cg_xr<T>, dim3(NBLK), dim3(RT), 0, c.s, x, r, p, q, c.scal, n, c.partial);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, 0, (int)FIN_CG_BETA);
+        hipLaunchKernelGGL(k_cg_p<T>, dim3(gb), dim3(256), 0, c.s, p, r, c.scal, n);
+        CK(hipGetLastError());
+        ++iters;
+        if (iters % check_every == 0 || iters == max_it) {
+            if (int e = read_scal(c, S_RR, rr)) return e;
+            if (!std::isfinite(rr)) { set_error("non-finite residual in CG"); return STDG_ERR_NUMERIC; }
+            res_out = std::sqrt(rr);
+            if (res_out <= tol_abs) return STDG_OK;
+        }
+    }
+    return STDG_NOT_CONVERGED;
+}
+
+// Restarted GMRES(m) with classical Gram-Schmidt applied twice.
+template <typename T>
+int gmres(Ctx& c, const T* b, T* x, T* r, T* V, int mres, double tol_abs, int max_it, int check_every,
+          int& iters, double& res_out) {
+    const int64_t n = c.n;
+    const int gb = grid_for(n);
+    double* H = c.gm;
+    double* g = H + (mres + 1) * mres;
+    double* cs = g + (mres + 1);
+    double* sn = cs + mres;
+    double* y = sn + mres;
+    double* h = y + mres;            // mres + 1 scratch dots
+    iters = 0;
+    while (true) {
+        // r = b - S x, beta = ||r||, V_0 = r / beta
+        CK(Apply<T>::run(c.m, x, r, c.s)); c.applies++;
+        hipLaunchKernelGGL((k_resid<T, T>), dim3(NBLK), dim3(RT), 0, c.s, b, r, V, n, c.partial);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_NORM, (int)FIN_SQRT);
+        double beta;
+        if (int e = read_scal(c, S_NORM, beta)) return e;
+        if (!std::isfinite(beta)) { set_error("non-finite residual in GMRES"); return STDG_ERR_NUMERIC; }
+        res_out = beta;
+        if (beta <= tol_abs) return STDG_OK;
+        if (iters >= max_it) return STDG_NOT_CONVERGED;
+        hipLaunchKernelGGL(k_scale_inv<T>, dim3(gb), dim3(256), 0, c.s, V, c.scal + S_NORM, n);
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid_for((mres + 1) * mres)), dim3(256), 0, c.s, H, 0.0,
+                           (int64_t)(mres + 1) * mres);
+        hipLaunchKernelGGL(k_init_g, dim3(1), dim3(256), 0, c.s, g, mres, c.scal + S_NORM);
+        int k = 0;
+        bool conv = false;
+        for (; k < mres && iters < max_it; ++k) {
+            T* w = V + (int64_t)(k + 1) * n;
+            CK(Apply<T>::run(c.m, V + (int64_t)k * n, w, c.s)); c.applies++;
+            double* Hk = H + (int64_t)(mres + 1) * k;
+            for (int pass = 0; pass < 2; ++pass) {
+                hipLaunchKernelGGL(k_multidot<T>, dim3(NBLK), dim3(RT), 0, c.s, V, k + 1, n, w, c.partial);
+                hipLaunchKernelGGL(k_fin_multi, dim3(k + 1), dim3(RT), 0, c.s, c.partial, NBLK, h, Hk, 1.0);
+                hipLaunchKernelGGL(k_multiaxpy<T>, dim3(gb), dim3(256), 0, c.s, V, k + 1, n, h, -1.0, w);
+            }
+            hipLaunchKernelGGL((k_dot<T, T>), dim3(NBLK), dim3(RT), 0, c.s, w, w, n, c.partial);
+            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, Hk, k + 1, (int)FIN_SQRT);
+            hipLaunchKernelGGL(k_scale_inv<T>, dim3(gb), dim3(256), 0, c.s, w, Hk + k + 1, n);
+            hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, c.s, H, g, cs, sn, k, mres, c.scal);
+            CK(hipGetLastError());
+            ++iters;
+            if ((k + 1) % check_every == 0 || k + 1 == mres || iters == max_it) {
+                double est;
+                if (int e = read_scal(c, S_RES, est)) return e;
+                if (!std::isfinite(est)) { set_error("non-finite residual in GMRES"); return STDG_ERR_NUMERIC; }
+                res_out = est;
+                if (est <= tol_abs) { conv = true; ++k; break; }
+            }
+        }
+        // x += V y
+        hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, c.s, H, g, y, k, mres);
+        hipLaunchKernelGGL(k_multiaxpy<T>, dim3(gb), dim3(256), 0, c.s, V, k, n, y, 1.0, x);
+        CK(hipGetLastError());
+        (void)conv;
+    }
+}
+
+template <typename T>
+int run_krylov(Ctx& c, int method, const T* b, T* x, T* r, T* p, T* q, T* V, int mres, double tol_abs,
+               int max_it, int check_every, int& iters, double& res) {
+    if (method == STDG_CG) return cg<T>(c, b, x, r, p, q, tol_abs, max_it, check_every, iters, res);
+    return gmres<T>(c, b, x, r, V, mres, tol_abs, max_it, check_every, iters, res);
+}
+
+int ensure_workspace(stdg_mesh* m, int mres, bool need32) {
+    Workspace& w = m->ws;
+    const size_t n = (size_t)m->E * m->Nst;
+    if (w.n != n) {
+        // first use on this mesh
+        w.n = n;
+        STDG_HIP(hipMalloc(&w.r, n * sizeof(double)));
+        STDG_HIP(hipMalloc(&w.p, n * sizeof(double)));
+        STDG_HIP(hipMalloc(&w.q, n * sizeof(double)));
+        STDG_HIP(hipMalloc(&w.z, n * sizeof(double)));
+        STDG_HIP(hipMalloc(&w.partial, sizeof(double) * NBLK * 208));
+        STDG_HIP(hipMalloc(&w.scal, sizeof(double) * (S_COUNT + 4 * 256 + 208 * 208)));
+        STDG_HIP(hipHostMalloc(&w.hscal, sizeof(double) * 8));
+    }
+    if (need32) {
+        for (float** f : {&w.r32, &w.p32, &w.q32, &w.x32, &w.b32})
+            if (!*f) STDG_HIP(hipMalloc(f, n * sizeof(float)));
+    }
+    if (mres > w.restart) {
+        if (w.V) STDG_HIP(hipFree(w.V));
+        if (w.V32) STDG_HIP(hipFree(w.V32));
+        w.V = nullptr; w.V32 = nullptr;
+        STDG_HIP(hipMalloc(&w.V, n * sizeof(double) * (mres + 1)));
+        w.restart = mres;
+    }
+    if (need32 && mres > 0 && !w.V32) STDG_HIP(hipMalloc(&w.V32, n * sizeof(float) * (w.restart + 1)));
+    return STDG_OK;
+}
+
+}  // namespace
+
+void free_workspace(stdg_mesh* m) {
+    Workspace& w = m->ws;
+    for (void* p : {(void*)w.r, (void*)w.p, (void*)w.q, (void*)w.z, (void*)w.V, (void*)w.r32, (void*)w.p32,
+                    (void*)w.q32, (void*)w.x32, (void*)w.b32, (void*)w.V32, (void*)w.partial, (void*)w.scal})
+        if (p) (void)hipFree(p);
+    if (w.hscal) (void)hipHostFree(w.hscal);
+    w = Workspace();
+}
+
+}  // namespace stdg
+
+using namespace stdg;
+
+extern "C" void stdg_solve_opts_default(stdg_solve_opts* o) {
+    if (!o) return;
+    o->method = STDG_AUTO;
+    o->restart = 50;
+    o->rtol = 1e-10;
+    o->max_iter = 20000;
+    o->precision = STDG_FP64;
+    o->inner_rtol = 1e-4;
+    o->max_outer = 30;
+    o->check_every = 8;
+}
+
+extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double* x,
+                                   const stdg_solve_opts* opts, stdg_solve_report* rep, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!cm || !b || !x || !opts) { set_error("null argument"); return STDG_ERR_ARG; }
+    stdg_mesh* m = const_cast<stdg_mesh*>(cm);
+    if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
+    stdg_solve_opts o = *opts;
+    if (o.method == STDG_AUTO) o.method = (m->G == 1) ? STDG_CG : STDG_GMRES;
+    if (o.method != STDG_CG && o.method != STDG_GMRES) { set_error("unknown method"); return STDG_ERR_ARG; }
+    if (o.method == STDG_GMRES && (o.restart < 1 || o.restart > 200)) { set_error("restart out of range"); return STDG_ERR_ARG; }
+    if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1) { set_error("bad tolerance/iteration options"); return STDG_ERR_ARG; }
+    if (o.precision != STDG_FP64 && o.precision != STDG_FP32) { set_error("bad precision"); return STDG_ERR_ARG; }
+    const bool ir = o.precision == STDG_FP32;
+    if (ir && (!(o.inner_rtol > 0.0) || o.max_outer < 1)) { set_error("bad refinement options"); return STDG_ERR_ARG; }
+    const int mres = (o.method == STDG_GMRES) ? o.restart : 0;
+    if (int e = ensure_workspace(m, mres, ir)) return e;
+    Workspace& w = m->ws;
+    Ctx c;
+    c.m = m;
+    c.s = (hipStream_t)stream;
+    c.n = (int64_t)w.n;
+    c.partial = w.partial;
+    c.scal = w.scal;
+    c.hscal = w.hscal;
+    c.gm = w.scal + S_COUNT;
+    const int64_t n = c.n;
+    const int gb = grid_for(n);
+    const int G = m->G, N = m->N;
+    // b~ (consistent right-hand side) in w.z
+    hipLaunchKernelGGL(k_copy<double>, dim3(gb), dim3(256), 0, c.s, b, w.z, n);
+    if (int e = time_sums(c, w.z)) return e;
+    hipLaunchKernelGGL(k_set_anchor, dim3(1), dim3(64), 0, c.s, w.z, c.scal + S_TIME, m->anchor, m->anchor_node, G, N);
+    // ||b_a||
+    hipLaunchKernelGGL(k_anch_res, dim3(NBLK), dim3(RT), 0, c.s, b, b, m->anchor, m->anchor_node, m->E, G, N, c.partial);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial + NBLK, NBLK, c.scal, (int)S_BN2, (int)FIN_STORE);
+    double bn2;
+    if (int e = read_scal(c, S_BN2, bn2)) return e;
+    if (!std::isfinite(bn2)) { set_error("non-finite right-hand side"); return STDG_ERR_NUMERIC; }
+    const double bnorm = std::sqrt(bn2);
+    int status = STDG_OK, inner_total = 0, outer = 0;
+    double rel = 0.0;
+    if (bnorm == 0.0) {
+        hipLaunchKernelGGL(k_fill<double>, dim3(gb), dim3(256), 0, c.s, x, 0.0, n);
+    } else if (!ir) {
+        int it = 0;
+        double res = 0.0;
+        outer = 1;
+        // the recursive residual may drift from the true one: restart from the
+        // true residual until the true anchored residual meets the tolerance
+        for (int round = 0; round < 5; ++round) {
+            int left = o.max_iter - inner_total;
+            if (left <= 0) { status = STDG_NOT_CONVERGED; break; }
+            status = run_krylov<double>(c, o.method, w.z, x, w.r, w.p, w.q, w.V, mres, o.rtol * bnorm,
+                                        left, o.check_every, it, res);
+            inner_total += it;
+            if (status < 0) return status;
+            CK(launch_apply_f64(m, x, w.q, c.s)); c.applies++;
+            hipLaunchKernelGGL((k_resid<double, double>), dim3(NBLK), dim3(RT), 0, c.s, w.z, w.q, w.r, n, c.partial);
+            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_RN2, (int)FIN_STORE);
+            double rn2;
+            if (int e = read_scal(c, S_RN2, rn2)) return e;
+            if (std::sqrt(rn2) <= o.rtol * bnorm || status == STDG_NOT_CONVERGED) break;
+        }
+    } else {
+        // FP64 iterative refinement around FP32 Krylov solves
+        for (outer = 1; outer <= o.max_outer; ++outer) {
+            CK(launch_apply_f64(m, x, w.q, c.s)); c.applies++;
+            hipLaunchKernelGGL((k_resid<double, double>), dim3(NBLK), dim3(RT), 0, c.s, w.z, w.q, w.r, n, c.partial);
+            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_RN2, (int)FIN_STORE);
+            double rn2;
+            if (int e = read_scal(c, S_RN2, rn2)) return e;
+            if (!std::isfinite(rn2)) { set_error("non-finite residual in refinement"); return STDG_ERR_NUMERIC; }
+            const double rn = std::sqrt(rn2);
+            if (rn <= o.rtol * bnorm) break;
+            if (inner_total >= o.max_iter) { status = STDG_NOT_CONVERGED; break; }
+            // inner right-hand side: r projected on the range of S, in FP32
+            if (int e = time_sums(c, w.r)) return e;
+            hipLaunchKernelGGL(k_remove_mean<double>, dim3(gb), dim3(256), 0, c.s, w.r, c.scal + S_TIME, m->E, G, N);
+            CK(convert_d2f(w.r, w.b32, n, c.s));
+            hipLaunchKernelGGL(k_fill<float>, dim3(gb), dim3(256), 0, c.s, w.x32, 0.0f, n);
+            int it = 0;
+            double res = 0.0;
+            status = run_krylov<float>(c, o.method, w.b32, w.x32, w.r32, w.p32, w.q32, w.V32, mres,
+                                       o.inner_rtol * rn, o.max_iter - inner_total, o.check_every, it, res);
+            inner_total += it;
+            if (status < 0) return status;
+            hipLaunchKernelGGL(k_add_f32, dim3(gb), dim3(256), 0, c.s, x, w.x32, n);
+            CK(hipGetLastError());
+            status = STDG_OK;
+        }
+        if (outer > o.max_outer) status = STDG_NOT_CONVERGED;
+    }
+    // shift so that x_anchor = 0 at every time node, then the exact anchored residual
+    hipLaunchKernelGGL(k_read_anchor, dim3(1), dim3(64), 0, c.s, x, c.scal + S_ANCH, m->anchor, m->anchor_node, G, N);
+    hipLaunchKernelGGL(k_shift, dim3(gb), dim3(256), 0, c.s, x, c.scal + S_ANCH, m->E, G, N);
+    CK(launch_apply_f64(m, x, w.q, c.s)); c.applies++;
+    hipLaunchKernelGGL(k_anch_res, dim3(NBLK), dim3(RT), 0, c.s, b, w.q, m->anchor, m->anchor_node, m->E, G, N, c.partial);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_RN2, (int)FIN_STORE);
+    double rn2 = 0.0;
+    if (bnorm > 0.0) {
+        if (int e = read_scal(c, S_RN2, rn2)) return e;
+        rel = std::sqrt(rn2) / bnorm;
+    }
+    CK(hipStreamSynchronize(c.s));
+    if (!std::isfinite(rel)) { set_error("non-finite final residual"); status = STDG_ERR_NUMERIC; }
+    if (status == STDG_OK && rel > o.rtol * 1.0000001) status = STDG_NOT_CONVERGED;
+    if (rep) {
+        rep->status = status;
+        rep->outer_iters = outer;
+        rep->inner_iters = inner_total;
+        rep->applies = c.applies;
+        rep->rel_residual = rel;
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}

@@ -1,0 +1,200 @@
+"""GPU parity of the pressure Schur operator and its solve against the oracle.
+
+All calls go through the C ABI (ctypes binding).  Tolerances: FP64 operator
+application 1e-12 relative (max-norm over the vector); pressure after a solve
+1e-8 relative; FP32 operator within 1e-5 relative of FP64.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from common import case_mesh, to_input
+from stdg_inputs import kuhn_mesh, node_coordinates
+from oracle.basis import TetMap, exponents, nodal_phys
+from oracle.mesh import Mesh as OracleMesh
+from oracle.pressure import apply_S, assemble_S, solve_anchored
+from oracle.quadrature import simplex_rule
+from oracle.spacetime import SpaceTimeOperators
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1601_07384_amd")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def gpu(v, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(v), dtype=dtype, device=DEV)
+
+
+def lib_apply(m, x_int, precision=P.STDG_FP64):
+    x = gpu(x_int.ravel())
+    y = torch.empty_like(x)
+    m.apply(x, y, precision=precision)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().reshape(m.E, m.Nst)
+
+
+SMALL = [  # n, p, p_gamma, periodic, jitter
+    (2, 1, 0, False, 0.0), (2, 2, 0, False, 0.15), (3, 2, 1, True, 0.0),
+    (3, 3, 0, False, 0.0), (2, 2, 2, False, 0.1), (3, 1, 3, True, 0.0),
+    (2, 4, 1, False, 0.0)]
+
+
+@pytest.mark.parametrize("n,p,pg,periodic,jitter", SMALL)
+def test_apply_matches_oracle_small(n, p, pg, periodic, jitter):
+    print(f"case n={n} p={p} pg={pg} periodic={periodic} jitter={jitter}", flush=True)
+    X, T = case_mesh(n, jitter=jitter)
+    m = P.Mesh(X, T, p, pg, dt=0.05, periodic=periodic)
+    ops = SpaceTimeOperators(OracleMesh(X, T, periodic=periodic), p, pg, 0.05)
+    x = np.random.default_rng(2).standard_normal((m.E, m.Nst))
+    yo = apply_S(ops, x)
+    perm = m.permutation()
+    yg = to_input(lib_apply(m, x[perm]), perm)
+    assert np.abs(yg - yo).max() <= 1e-12 * np.abs(yo).max()
+
+
+def test_apply_c1_full_mesh():
+    """6^3 x 6 = 1,296 tets, p=2, p_gamma=0, Dirichlet, dt=1e-2: every row."""
+    print("case C1 full", flush=True)
+    X, T = kuhn_mesh(6)
+    m = P.Mesh(X, T, 2, 0, dt=1e-2)
+    ops = SpaceTimeOperators(OracleMesh(X, T), 2, 0, 1e-2)
+    x = np.random.default_rng(4).standard_normal((m.E, m.Nst))
+    yo = apply_S(ops, x)
+    perm = m.permutation()
+    yg = to_input(lib_apply(m, x[perm]), perm)
+    assert np.abs(yg - yo).max() <= 1e-12 * np.abs(yo).max()
+
+
+def _sampled_rows(n, p, pg, periodic, dt, n_samples, seed):
+    X, T = kuhn_mesh(n)
+    m = P.Mesh(X, T, p, pg, dt=dt, periodic=periodic)
+    om = OracleMesh(X, T, periodic=periodic)
+    ops = SpaceTimeOperators(om, p, pg, dt)
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((m.E, m.Nst))
+    perm = m.permutation()
+    yg = to_input(lib_apply(m, x[perm]), perm)
+    rows = rng.choice(m.E, size=n_samples, replace=False)
+    rows = np.concatenate([rows, [0, m.E - 1]])
+    yo = apply_S(ops, x, elements=rows)
+    scale = np.abs(yo[rows]).max()
+    return np.abs(yg[rows] - yo[rows]).max() / scale
+
+
+def test_apply_c2_full_size_sampled_rows():
+    """24^3 x 6 = 82,944 tets, p=3, p_gamma=1, periodic: sampled rows."""
+    print("case C2 sampled", flush=True)
+    assert _sampled_rows(24, 3, 1, True, 1e-3, 24, 5) <= 1e-12
+
+
+def test_apply_c4_full_size_sampled_rows():
+    """16^3 x 6 = 24,576 tets, p=4, p_gamma=4, Dirichlet: sampled rows."""
+    print("case C4 sampled", flush=True)
+    assert _sampled_rows(16, 4, 4, False, 1e-2, 6, 6) <= 1e-12
+
+
+def test_apply_c3_full_size_properties():
+    """48^3 x 6 = 663,552 tets, p=3, p_gamma=0, periodic: S 1 = 0, symmetry
+    <Sx, z> = <x, Sz>, and the Green closed form S q = -dt^2 int phi Lap q for
+    a quadratic pressure on elements away from the periodic seam."""
+    print("case C3 properties", flush=True)
+    n, p, dt = 48, 3, 1e-3
+    X, T = kuhn_mesh(n)
+    m = P.Mesh(X, T, p, 0, dt=dt, periodic=True)
+    perm = m.permutation()
+    rng = np.random.default_rng(9)
+    one = np.ones((m.E, m.Nst))
+    y1 = lib_apply(m, one)
+    x = rng.standard_normal((m.E, m.Nst))
+    z = rng.standard_normal((m.E, m.Nst))
+    sx, sz = lib_apply(m, x), lib_apply(m, z)
+    assert np.abs(y1).max() <= 1e-12 * np.abs(sx).max()
+    a, b = np.vdot(sx, z), np.vdot(x, sz)
+    assert abs(a - b) <= 1e-12 * np.linalg.norm(sx) * np.linalg.norm(z)
+    # quadratic pressure q = x^2 + 2 y^2 - z^2 + xy: Lap q = 2 + 4 - 2 = 4
+    xn = node_coordinates(X, T, p)                        # input order
+    q = xn[..., 0] ** 2 + 2 * xn[..., 1] ** 2 - xn[..., 2] ** 2 + xn[..., 0] * xn[..., 1]
+    yq = to_input(lib_apply(m, q[perm]), perm)
+    from oracle.basis import NodalBasis
+    phi = NodalBasis(p)
+    cent = X[T].mean(axis=1)
+    inner = np.where(np.all((cent > 2.0 / n) & (cent < 1 - 2.0 / n), axis=1))[0]
+    for e in rng.choice(inner, size=32, replace=False):
+        v = X[T[e]]
+        xq, wq = simplex_rule(v, p)
+        ph, _ = nodal_phys(phi, TetMap(v), xq)
+        expect = -dt * dt * 4.0 * (wq[:, None] * ph).sum(0)
+        assert np.abs(yq[e] - expect).max() <= 1e-9 * np.abs(expect).max()
+
+
+def test_apply_fp32_close_to_fp64():
+    X, T = case_mesh(4)
+    m = P.Mesh(X, T, 3, 1, dt=1e-2, periodic=True)
+    x = np.random.default_rng(3).standard_normal((m.E, m.Nst))
+    y64 = lib_apply(m, x)
+    y32 = lib_apply(m, x, precision=P.STDG_FP32)
+    assert np.abs(y32 - y64).max() <= 1e-5 * np.abs(y64).max()
+    xf = gpu(x.ravel(), torch.float32)
+    yf = torch.empty_like(xf)
+    m.apply_f32(xf, yf)
+    torch.cuda.synchronize()
+    assert np.abs(yf.cpu().numpy().reshape(y64.shape) - y64).max() <= 1e-5 * np.abs(y64).max()
+
+
+def test_apply_bitwise_reproducible():
+    X, T = case_mesh(5)
+    m = P.Mesh(X, T, 2, 1, dt=1e-2, periodic=True)
+    x = np.random.default_rng(1).standard_normal((m.E, m.Nst))
+    assert np.array_equal(lib_apply(m, x), lib_apply(m, x))
+
+
+# --------------------------------------------------------------------- solve
+SOLVE = [  # n, p, pg, periodic, jitter, method, precision
+    (6, 2, 0, False, 0.0, P.STDG_CG, P.STDG_FP64),       # C1 mesh and degree
+    (6, 2, 0, False, 0.0, P.STDG_CG, P.STDG_FP32),
+    (3, 2, 1, False, 0.1, P.STDG_GMRES, P.STDG_FP64),
+    (3, 2, 1, True, 0.0, P.STDG_GMRES, P.STDG_FP32),
+    (3, 1, 2, False, 0.0, P.STDG_GMRES, P.STDG_FP64),
+]
+
+
+@pytest.mark.parametrize("n,p,pg,periodic,jitter,method,precision", SOLVE)
+def test_solve_matches_oracle(n, p, pg, periodic, jitter, method, precision):
+    print(f"solve n={n} p={p} pg={pg} periodic={periodic} method={method} prec={precision}", flush=True)
+    X, T = case_mesh(n, jitter=jitter)
+    dt = 1e-2
+    m = P.Mesh(X, T, p, pg, dt=dt, periodic=periodic)
+    ops = SpaceTimeOperators(OracleMesh(X, T, periodic=periodic), p, pg, dt)
+    S = assemble_S(ops)
+    rng = np.random.default_rng(12)
+    # a right-hand side in the range of S plus a small incompatible part
+    xt = rng.standard_normal(S.shape[0])
+    b = S @ xt + 1e-3 * np.abs(S @ xt).max() * rng.standard_normal(S.shape[0])
+    xo = solve_anchored(ops, S, b).reshape(m.E, m.Nst)
+    perm = m.permutation()
+    bg = gpu(b.reshape(m.E, m.Nst)[perm].ravel())
+    xg = torch.zeros_like(bg)
+    rep = m.solve(bg, xg, method=method, precision=precision, rtol=1e-12, restart=40)
+    assert rep.status == 0, (rep.status, rep.rel_residual, rep.inner_iters)
+    assert rep.rel_residual <= 1e-12
+    xs = to_input(xg.cpu().numpy().reshape(m.E, m.Nst), perm)
+    assert np.abs(xs - xo).max() <= 1e-8 * np.abs(xo).max()
+
+
+def test_solve_reports_not_converged_and_nan():
+    X, T = case_mesh(3)
+    m = P.Mesh(X, T, 2, 0, dt=1e-2)
+    b = gpu(np.random.default_rng(0).standard_normal(m.E * m.Nst))
+    x = torch.zeros_like(b)
+    rep = m.solve(b, x, max_iter=1, check_every=1)
+    assert rep.status == P.STDG_NOT_CONVERGED
+    b[5] = float("nan")
+    x.zero_()
+    with pytest.raises(P.StdgError) as e:
+        m.solve(b, x)
+    assert e.value.code == -3

@@ -1,0 +1,117 @@
+"""CPU tests of the library: exported symbols, host-side tables, error paths.
+
+No device computation runs here: meshes are built with stdg_mesh_build_host.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from common import blocks_apply, case_mesh, to_input
+from oracle.mesh import Mesh as OracleMesh
+from oracle.pressure import apply_S
+from oracle.spacetime import SpaceTimeOperators
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+P = pytest.importorskip("paper_1601_07384_amd")
+from paper_1601_07384_amd import _lib  # noqa: E402
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(stdg_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = declared_symbols()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    bound = {s[0] for s in _lib.SIGNATURES}
+    assert names <= bound, names - bound
+
+
+@pytest.mark.parametrize("n,p,pg,periodic,jitter", [
+    (2, 2, 0, False, 0.0), (2, 1, 1, False, 0.15), (3, 2, 1, True, 0.0),
+    (2, 3, 0, False, 0.1), (2, 2, 2, False, 0.0)])
+def test_host_tables_match_oracle(n, p, pg, periodic, jitter):
+    """The library's Kronecker-factored blocks reproduce the oracle's literal
+    space-time operator (eq. CS_19) to 1e-12 relative."""
+    X, T = case_mesh(n, jitter=jitter)
+    m = P.Mesh(X, T, p, pg, dt=0.05, periodic=periodic, device=False)
+    ops = SpaceTimeOperators(OracleMesh(X, T, periodic=periodic), p, pg, 0.05)
+    x = np.random.default_rng(1).standard_normal((m.E, m.Nst))
+    yo = apply_S(ops, x)
+    perm = m.permutation()
+    yp = to_input(blocks_apply(m, x[perm]), perm)
+    assert np.abs(yp - yo).max() <= 1e-12 * np.abs(yo).max()
+
+
+def test_kuhn_classes_and_face_counts():
+    """A periodic Kuhn mesh has 6 translation classes; face counts 12 n^3
+    (periodic) and 12 n^3 - 6 n^2 interior + 12 n^2 boundary (Dirichlet)."""
+    X, T = case_mesh(4)
+    per = P.Mesh(X, T, 2, 0, periodic=True, device=False)
+    assert per.n_classes == 6
+    assert per.n_face == per.n_interior_face == 12 * 64
+    dr = P.Mesh(X, T, 2, 0, periodic=False, device=False)
+    assert dr.n_interior_face == 12 * 64 - 6 * 16
+    assert dr.n_face - dr.n_interior_face == 12 * 16
+
+
+def test_hilbert_permutation_is_a_permutation():
+    X, T = case_mesh(3)
+    m = P.Mesh(X, T, 1, 0, device=False)
+    perm = m.permutation()
+    assert sorted(perm.tolist()) == list(range(T.shape[0]))
+    m0 = P.Mesh(X, T, 1, 0, device=False, reorder=False)
+    assert (m0.permutation() == np.arange(T.shape[0])).all()
+
+
+def test_error_paths():
+    X, T = case_mesh(2)
+    with pytest.raises(P.StdgError) as e:
+        P.Mesh(X, T, 0, 0, device=False)
+    assert e.value.code == _lib.STDG_ERR_ARG
+    with pytest.raises(P.StdgError) as e:
+        P.Mesh(X, T, 2, 0, dt=-1.0, device=False)
+    assert e.value.code == _lib.STDG_ERR_ARG
+    # flat element
+    Xf = X.copy()
+    T2 = T.copy()
+    T2[0, 3] = T2[0, 2]
+    with pytest.raises(P.StdgError) as e:
+        P.Mesh(Xf, T2, 1, 0, device=False)
+    assert e.value.code == _lib.STDG_ERR_MESH
+    # non-manifold face: duplicate an element
+    T3 = np.vstack([T, T[:1]])
+    with pytest.raises(P.StdgError) as e:
+        P.Mesh(X, T3, 1, 0, device=False)
+    assert e.value.code == _lib.STDG_ERR_MESH
+    # unmatched periodic face: a box that does not match the mesh
+    with pytest.raises(P.StdgError) as e:
+        P.Mesh(X, T, 1, 0, periodic=True, box_hi=(2.0, 1.0, 1.0), device=False)
+    assert e.value.code == _lib.STDG_ERR_MESH
+    # vertex index out of range
+    T4 = T.copy(); T4[1, 1] = 10 ** 6
+    with pytest.raises(P.StdgError) as e:
+        P.Mesh(X, T4, 1, 0, device=False)
+    assert e.value.code == _lib.STDG_ERR_ARG
+
+
+def test_device_entry_points_reject_host_only_handle():
+    X, T = case_mesh(2)
+    m = P.Mesh(X, T, 1, 0, device=False)
+    lib = _lib.load()
+    code = lib.stdg_pressure_apply(m._h, 0, ctypes.c_void_p(8), ctypes.c_void_p(16), None)
+    assert code == _lib.STDG_ERR_ARG
