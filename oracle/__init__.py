@@ -21,6 +21,8 @@ unstructured tetrahedral meshes" (arXiv 1601.07384):
 * picard.py      - the Picard pressure-correction step (Sec. 2.6, steps 0-6).
 * mlp.py         - the multilayer perceptron used as a Krylov initial guess.
 
-Every number is float64.  Nothing here is blocked, fused or reordered beyond
-what the paper's definitions state.
+Matrices are evaluated in numpy.longdouble (x87 80-bit) and results returned
+as float64: the dual mass matrices of the Taylor basis are ill-conditioned at
+high degree (condition numbers near 1e10 at p = 4).  Nothing here is blocked,
+fused or reordered beyond what the paper's definitions state.
 """

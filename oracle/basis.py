@@ -15,6 +15,7 @@ functions.
 
 import numpy as np
 
+from .linalg import REAL, asreal, det3, inv
 from .quadrature import gauss_legendre_01
 
 
@@ -30,8 +31,8 @@ def exponents(p):
 
 def nodal_points(p):
     """(N, 3) reference nodes (j1, j2, j3)/p."""
-    e = exponents(p).astype(np.float64)
-    return e / p if p > 0 else e
+    e = exponents(p).astype(REAL)
+    return e / REAL(p) if p > 0 else e
 
 
 def _monomials(pts, ex):
@@ -42,7 +43,7 @@ def _monomials(pts, ex):
 def _monomial_grads(pts, ex):
     """(m, N, 3) gradients of x^r."""
     m, N = pts.shape[0], ex.shape[0]
-    g = np.zeros((m, N, 3))
+    g = np.zeros((m, N, 3), dtype=pts.dtype)
     for d in range(3):
         ed = ex.copy()
         coef = ed[:, d].astype(np.float64)
@@ -56,7 +57,7 @@ def nodal_coefficients(p):
     ex = exponents(p)
     V = _monomials(nodal_points(p), ex)          # V[j, r] = xi_j^r
     # alpha V^T = I
-    return np.linalg.inv(V.T)
+    return inv(V.T)
 
 
 class NodalBasis:
@@ -70,11 +71,11 @@ class NodalBasis:
 
     def eval(self, xi):
         """Values (m, N) at reference points xi (m, 3)."""
-        return _monomials(np.atleast_2d(xi), self.ex) @ self.alpha.T
+        return _monomials(np.atleast_2d(asreal(xi)), self.ex) @ self.alpha.T
 
     def grad_ref(self, xi):
         """Reference gradients (m, N, 3)."""
-        g = _monomial_grads(np.atleast_2d(xi), self.ex)   # (m, R, 3)
+        g = _monomial_grads(np.atleast_2d(asreal(xi)), self.ex)   # (m, R, 3)
         return np.einsum("kr,mrd->mkd", self.alpha, g)
 
 
@@ -82,13 +83,13 @@ class TetMap:
     """Affine map of a tetrahedron with vertices v (4, 3) (Sec. 2.3)."""
 
     def __init__(self, v):
-        self.v = np.asarray(v, dtype=np.float64)
+        self.v = asreal(v)
         self.J = (self.v[1:] - self.v[0]).T          # x = v0 + J xi
-        self.Jinv = np.linalg.inv(self.J)
-        self.detJ = np.linalg.det(self.J)
+        self.Jinv = inv(self.J)
+        self.detJ = det3(self.J)
 
     def to_ref(self, x):
-        return (np.atleast_2d(x) - self.v[0]) @ self.Jinv.T
+        return (np.atleast_2d(asreal(x)) - self.v[0]) @ self.Jinv.T
 
     def to_phys(self, xi):
         return self.v[0] + np.atleast_2d(xi) @ self.J.T
@@ -114,11 +115,11 @@ class TaylorBasis:
         self.p = p
         self.ex = exponents(p)
         self.N = self.ex.shape[0]
-        self.x0 = np.asarray(x0, dtype=np.float64)
-        self.h = float(h)
+        self.x0 = asreal(x0)
+        self.h = REAL(h)
 
     def eval(self, x):
-        y = (np.atleast_2d(x) - self.x0) / self.h
+        y = (np.atleast_2d(asreal(x)) - self.x0) / self.h
         return _monomials(y, self.ex)
 
 
@@ -129,17 +130,17 @@ class TimeBasis:
         self.G = G
         self.nodes, self.weights = gauss_legendre_01(G)
         V = np.vander(self.nodes, G, increasing=True)   # V[a, r] = tau_a^r
-        self.coef = np.linalg.inv(V).T                   # gamma_a = sum_r coef[a, r] tau^r
+        self.coef = inv(V).T                             # gamma_a = sum_r coef[a, r] tau^r
 
     def eval(self, tau):
-        tau = np.atleast_1d(np.asarray(tau, dtype=np.float64))
+        tau = np.atleast_1d(asreal(tau))
         P = np.vander(tau, self.G, increasing=True)
         return P @ self.coef.T                           # (m, G)
 
     def deriv(self, tau):
-        tau = np.atleast_1d(np.asarray(tau, dtype=np.float64))
+        tau = np.atleast_1d(asreal(tau))
         G = self.G
-        D = np.zeros((tau.size, G))
+        D = np.zeros((tau.size, G), dtype=REAL)
         for r in range(1, G):
             D[:, r] = r * tau ** (r - 1)
         return D @ self.coef.T

@@ -12,6 +12,8 @@ element; a boundary face's dual element is the single sub-tetrahedron.
 
 import numpy as np
 
+from .linalg import asreal, cross, norm
+
 
 class Mesh:
     def __init__(self, X, tets, periodic=False, box_lo=(0, 0, 0), box_hi=(1, 1, 1)):
@@ -100,18 +102,18 @@ class Mesh:
 
     def normal(self, j):
         """Unit normal of face j pointing out of the left element."""
-        P = self.face_vertices(j)
-        n = np.cross(P[1] - P[0], P[2] - P[0])
-        n /= np.linalg.norm(n)
-        c = self.tet_vertices(self.left[j]).mean(axis=0)
+        P = asreal(self.face_vertices(j))
+        n = cross(P[1] - P[0], P[2] - P[0])
+        n /= norm(n)
+        c = asreal(self.tet_vertices(self.left[j])).mean(axis=0)
         if n @ (P[0] - c) < 0:
             n = -n
         return n
 
     def subtet(self, j, side):
         """Sub-tetrahedron T_{i,j} (4, 3): the face and the element's barycentre."""
-        P = self.face_vertices(j)
-        bary = self.side_vertices(j, side).mean(axis=0)
+        P = asreal(self.face_vertices(j))
+        bary = asreal(self.side_vertices(j, side)).mean(axis=0)
         return np.vstack([P, bary[None, :]])
 
     def neighbour(self, t, f):

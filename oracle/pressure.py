@@ -19,6 +19,8 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from . import linalg
+
 
 def interior_faces(mesh):
     return [j for j in range(mesh.F) if mesh.right[j] >= 0]
@@ -31,7 +33,7 @@ def apply_S(ops, x, elements=None):
     other rows of the result are left at zero).
     """
     mesh = ops.mesh
-    x = np.asarray(x, dtype=np.float64).reshape(mesh.E, ops.Nst)
+    x = linalg.asreal(x).reshape(mesh.E, ops.Nst)
     y = np.zeros_like(x)
     if elements is None:
         faces = interior_faces(mesh)
@@ -44,13 +46,13 @@ def apply_S(ops, x, elements=None):
         F = ops.face(j)
         # momentum-equation velocity response to the pressure on both sides
         g = sum(np.einsum("dkl,l->dk", F[("Q", s)], x[F[("elem", s)]]) for s in (0, 1))
-        w = np.linalg.solve(F["M"], g.T).T          # M_j^-1 per component
+        w = linalg.solve(F["M"], g.T).T             # M_j^-1 per component
         for s in (0, 1):
             i = F[("elem", s)]
             if want is not None and i not in want:
                 continue
             y[i] -= np.einsum("dkl,dl->k", F[("D", s)], w)
-    return y
+    return y.astype(np.float64)
 
 
 def assemble_S(ops):
@@ -60,14 +62,15 @@ def assemble_S(ops):
     rows, cols, vals = [], [], []
     for j in interior_faces(mesh):
         F = ops.face(j)
-        Minv = np.linalg.inv(F["M"])
+        Minv = linalg.inv(F["M"])
         for s in (0, 1):
             for t in (0, 1):
                 blk = -np.einsum("dkl,lm,dmn->kn", F[("D", s)], Minv, F[("Q", t)])
                 i, k = F[("elem", s)], F[("elem", t)]
                 r, c = np.meshgrid(np.arange(Nst) + i * Nst, np.arange(Nst) + k * Nst,
                                    indexing="ij")
-                rows.append(r.ravel()); cols.append(c.ravel()); vals.append(blk.ravel())
+                rows.append(r.ravel()); cols.append(c.ravel())
+                vals.append(blk.ravel().astype(np.float64))
     n = mesh.E * Nst
     return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                          shape=(n, n))

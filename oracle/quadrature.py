@@ -19,6 +19,8 @@ import math
 import numpy as np
 from scipy.special import roots_jacobi
 
+from .linalg import REAL, asreal, cross, det3, norm
+
 
 def _compositions(total, parts):
     """All tuples of `parts` non-negative integers summing to `total`."""
@@ -36,17 +38,19 @@ def grundmann_moeller(n, s):
     """Points (m, n) and weights (m,) on {x >= 0, sum x <= 1} in R^n.
 
     Degree of exactness 2s+1; weights sum to the simplex volume 1/n!.
+    Computed in numpy.longdouble (weights from exact integer ratios).
     """
     d = 2 * s + 1
     pts, wts = [], []
     for i in range(s + 1):
-        w = ((-1) ** i) * 2.0 ** (-2 * s) * (d + n - 2 * i) ** d \
-            / (math.factorial(i) * math.factorial(d + n - i))
+        num = ((-1) ** i) * (d + n - 2 * i) ** d
+        den = 4 ** s * math.factorial(i) * math.factorial(d + n - i)
+        w = REAL(num) / REAL(den)
         for beta in _compositions(s - i, n + 1):
-            bary = [(2 * b + 1) / (d + n - 2 * i) for b in beta]
+            bary = [REAL(2 * b + 1) / REAL(d + n - 2 * i) for b in beta]
             pts.append(bary[1:])
             wts.append(w)
-    return np.asarray(pts, dtype=np.float64), np.asarray(wts, dtype=np.float64)
+    return np.asarray(pts, dtype=REAL), np.asarray(wts, dtype=REAL)
 
 
 def simplex_rule(vertices, s):
@@ -55,27 +59,46 @@ def simplex_rule(vertices, s):
     vertices: (n+1, n) array.  Returns physical points (m, n) and weights (m,)
     that already include the volume factor |det J|.
     """
-    vertices = np.asarray(vertices, dtype=np.float64)
+    vertices = asreal(vertices)
     n = vertices.shape[1]
     ref, w = grundmann_moeller(n, s)
     J = (vertices[1:] - vertices[0]).T           # columns: edges from vertex 0
     pts = vertices[0] + ref @ J.T
-    return pts, w * abs(np.linalg.det(J))
+    dj = det3(J) if n == 3 else J[0, 0] * J[1, 1] - J[0, 1] * J[1, 0]
+    return pts, w * abs(dj)
 
 
 def triangle_rule_3d(P, s):
     """Grundmann-Moeller rule on a triangle P (3, 3) embedded in R^3."""
-    P = np.asarray(P, dtype=np.float64)
+    P = asreal(P)
     ref, w = grundmann_moeller(2, s)
     e1, e2 = P[1] - P[0], P[2] - P[0]
     pts = P[0] + np.outer(ref[:, 0], e1) + np.outer(ref[:, 1], e2)
-    return pts, w * np.linalg.norm(np.cross(e1, e2))
+    return pts, w * norm(cross(e1, e2))
+
+
+def _legendre(n, x):
+    """P_n(x) and P_n'(x) by the three-term recurrence."""
+    p0, p1 = np.ones_like(x), x
+    if n == 0:
+        return p0, np.zeros_like(x)
+    for k in range(2, n + 1):
+        p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+    dp = n * (x * p1 - p0) / (x * x - 1)
+    return p1, dp
 
 
 def gauss_legendre_01(m):
-    """Gauss-Legendre nodes and weights on [0, 1]."""
-    x, w = np.polynomial.legendre.leggauss(m)
-    return 0.5 * (x + 1.0), 0.5 * w
+    """Gauss-Legendre nodes and weights on [0, 1] (longdouble: the float64
+    nodes are refined by Newton steps on P_m)."""
+    x0, _ = np.polynomial.legendre.leggauss(m)
+    x = asreal(x0)
+    for _ in range(4):
+        p, dp = _legendre(m, x)
+        x = x - p / dp
+    _, dp = _legendre(m, x)
+    w = REAL(2) / ((1 - x * x) * dp * dp)
+    return REAL(0.5) * (x + 1), REAL(0.5) * w
 
 
 def collapsed_triangle_rule(q):

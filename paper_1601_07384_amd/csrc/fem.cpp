@@ -7,43 +7,43 @@
 
 namespace stdg {
 
-double norm(const V3& a) { return std::sqrt(dot(a, a)); }
-double det3(const V3& c0, const V3& c1, const V3& c2) { return dot(c0, cross(c1, c2)); }
+real norm(const V3& a) { return std::sqrt(dot(a, a)); }
+real det3(const V3& c0, const V3& c1, const V3& c2) { return dot(c0, cross(c1, c2)); }
 
 // Symmetric eigen-decomposition of a small dense matrix by cyclic Jacobi
 // rotations.  A (n x n, row-major) is destroyed; eigenvalues in d, the
 // eigenvectors in the columns of V.
-static void sym_eig(int n, std::vector<double>& A, std::vector<double>& d,
-                    std::vector<double>& V) {
+static void sym_eig(int n, std::vector<real>& A, std::vector<real>& d,
+                    std::vector<real>& V) {
     V.assign(n * n, 0.0);
     for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
     for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0, tot = 0.0;
+        real off = 0.0, tot = 0.0;
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) {
                 tot += A[i * n + j] * A[i * n + j];
                 if (i != j) off += A[i * n + j] * A[i * n + j];
             }
-        if (off <= 1e-32 * tot) break;
+        if (off <= 1e-40L * tot) break;
         for (int p = 0; p < n; ++p)
             for (int q = p + 1; q < n; ++q) {
-                double apq = A[p * n + q];
+                real apq = A[p * n + q];
                 if (apq == 0.0) continue;
-                double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
-                double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-                double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                real theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                real t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                real c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
                 for (int k = 0; k < n; ++k) {      // A <- A R
-                    double akp = A[k * n + p], akq = A[k * n + q];
+                    real akp = A[k * n + p], akq = A[k * n + q];
                     A[k * n + p] = c * akp - s * akq;
                     A[k * n + q] = s * akp + c * akq;
                 }
                 for (int k = 0; k < n; ++k) {      // A <- R^T A
-                    double apk = A[p * n + k], aqk = A[q * n + k];
+                    real apk = A[p * n + k], aqk = A[q * n + k];
                     A[p * n + k] = c * apk - s * aqk;
                     A[q * n + k] = s * apk + c * aqk;
                 }
                 for (int k = 0; k < n; ++k) {      // V <- V R
-                    double vkp = V[k * n + p], vkq = V[k * n + q];
+                    real vkp = V[k * n + p], vkq = V[k * n + q];
                     V[k * n + p] = c * vkp - s * vkq;
                     V[k * n + q] = s * vkp + c * vkq;
                 }
@@ -53,25 +53,25 @@ static void sym_eig(int n, std::vector<double>& A, std::vector<double>& d,
     for (int i = 0; i < n; ++i) d[i] = A[i * n + i];
 }
 
-void gauss_jacobi(int n, double alpha, double beta, std::vector<double>& x,
-                  std::vector<double>& w) {
-    std::vector<double> J(n * n, 0.0);
-    const double ab = alpha + beta;
+void gauss_jacobi(int n, real alpha, real beta, std::vector<real>& x,
+                  std::vector<real>& w) {
+    std::vector<real> J(n * n, 0.0);
+    const real ab = alpha + beta;
     for (int k = 0; k < n; ++k) {
-        double a;
+        real a;
         if (k == 0) a = (beta - alpha) / (ab + 2.0);
         else a = (beta * beta - alpha * alpha) / ((2 * k + ab) * (2 * k + ab + 2.0));
         J[k * n + k] = a;
         if (k + 1 < n) {
-            const double m = k + 1;
-            double b = 4.0 * m * (m + alpha) * (m + beta) * (m + ab) /
+            const real m = k + 1;
+            real b = 4.0 * m * (m + alpha) * (m + beta) * (m + ab) /
                        ((2 * m + ab) * (2 * m + ab) * (2 * m + ab + 1.0) * (2 * m + ab - 1.0));
             J[k * n + k + 1] = J[(k + 1) * n + k] = std::sqrt(b);
         }
     }
-    std::vector<double> d, V;
+    std::vector<real> d, V;
     sym_eig(n, J, d, V);
-    const double mu0 = std::pow(2.0, ab + 1.0) * std::tgamma(alpha + 1.0) *
+    const real mu0 = std::pow((real)2, ab + 1) * std::tgamma(alpha + 1.0) *
                        std::tgamma(beta + 1.0) / std::tgamma(ab + 2.0);
     std::vector<int> idx(n);
     std::iota(idx.begin(), idx.end(), 0);
@@ -80,12 +80,12 @@ void gauss_jacobi(int n, double alpha, double beta, std::vector<double>& x,
     w.resize(n);
     for (int i = 0; i < n; ++i) {
         x[i] = d[idx[i]];
-        double v0 = V[0 * n + idx[i]];
+        real v0 = V[0 * n + idx[i]];
         w[i] = mu0 * v0 * v0;
     }
 }
 
-void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
+void gauss_legendre01(int n, std::vector<real>& x, std::vector<real>& w) {
     gauss_jacobi(n, 0.0, 0.0, x, w);
     for (int i = 0; i < n; ++i) {
         x[i] = 0.5 * (x[i] + 1.0);
@@ -93,10 +93,10 @@ void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
     }
 }
 
-static void jacobi01(int n, double alpha, std::vector<double>& x, std::vector<double>& w) {
+static void jacobi01(int n, real alpha, std::vector<real>& x, std::vector<real>& w) {
     // weight (1-u)^alpha on [0, 1]
     gauss_jacobi(n, alpha, 0.0, x, w);
-    const double s = std::pow(2.0, alpha + 1.0);
+    const real s = std::pow((real)2, alpha + 1);
     for (int i = 0; i < n; ++i) {
         x[i] = 0.5 * (x[i] + 1.0);
         w[i] /= s;
@@ -104,7 +104,7 @@ static void jacobi01(int n, double alpha, std::vector<double>& x, std::vector<do
 }
 
 Rule tet_rule(int q) {
-    std::vector<double> xu, wu, xv, wv, xw, ww;
+    std::vector<real> xu, wu, xv, wv, xw, ww;
     jacobi01(q, 2.0, xu, wu);
     jacobi01(q, 1.0, xv, wv);
     gauss_legendre01(q, xw, ww);
@@ -112,7 +112,7 @@ Rule tet_rule(int q) {
     for (int i = 0; i < q; ++i)
         for (int j = 0; j < q; ++j)
             for (int k = 0; k < q; ++k) {
-                double u = xu[i], v = xv[j], s = xw[k];
+                real u = xu[i], v = xv[j], s = xw[k];
                 r.pts.push_back({u, v * (1.0 - u), s * (1.0 - u) * (1.0 - v)});
                 r.w.push_back(wu[i] * wv[j] * ww[k]);
             }
@@ -120,7 +120,7 @@ Rule tet_rule(int q) {
 }
 
 Rule tri_rule(int q) {
-    std::vector<double> xu, wu, xv, wv;
+    std::vector<real> xu, wu, xv, wv;
     jacobi01(q, 1.0, xu, wu);
     gauss_legendre01(q, xv, wv);
     Rule r;
@@ -140,8 +140,8 @@ std::vector<std::array<int, 3>> exponents(int p) {
     return e;
 }
 
-static inline double ipow(double x, int k) {
-    double r = 1.0;
+static inline real ipow(real x, int k) {
+    real r = 1.0;
     for (int i = 0; i < k; ++i) r *= x;
     return r;
 }
@@ -150,9 +150,9 @@ NodalBasis::NodalBasis(int p_) : p(p_) {
     ex = exponents(p);
     N = (int)ex.size();
     // VT[r][j] = xi_j^r ; coef = VT^{-1} so that coef * VT = I  (phi_k(xi_j) = delta)
-    std::vector<double> VT(N * N);
+    std::vector<real> VT(N * N);
     for (int j = 0; j < N; ++j) {
-        V3 xi = {double(ex[j][0]) / p, double(ex[j][1]) / p, double(ex[j][2]) / p};
+        V3 xi = {real(ex[j][0]) / p, real(ex[j][1]) / p, real(ex[j][2]) / p};
         for (int r = 0; r < N; ++r)
             VT[r * N + j] = ipow(xi[0], ex[r][0]) * ipow(xi[1], ex[r][1]) * ipow(xi[2], ex[r][2]);
     }
@@ -161,19 +161,19 @@ NodalBasis::NodalBasis(int p_) : p(p_) {
     coef = VT;
 }
 
-void NodalBasis::eval(const V3& xi, double* val) const {
-    std::vector<double> mono(N);
+void NodalBasis::eval(const V3& xi, real* val) const {
+    std::vector<real> mono(N);
     for (int r = 0; r < N; ++r)
         mono[r] = ipow(xi[0], ex[r][0]) * ipow(xi[1], ex[r][1]) * ipow(xi[2], ex[r][2]);
     for (int k = 0; k < N; ++k) {
-        double s = 0.0;
+        real s = 0.0;
         for (int r = 0; r < N; ++r) s += coef[k * N + r] * mono[r];
         val[k] = s;
     }
 }
 
-void NodalBasis::grad(const V3& xi, double* g) const {
-    std::vector<double> dm(3 * N);
+void NodalBasis::grad(const V3& xi, real* g) const {
+    std::vector<real> dm(3 * N);
     for (int r = 0; r < N; ++r) {
         const auto& e = ex[r];
         dm[3 * r + 0] = e[0] ? e[0] * ipow(xi[0], e[0] - 1) * ipow(xi[1], e[1]) * ipow(xi[2], e[2]) : 0.0;
@@ -182,7 +182,7 @@ void NodalBasis::grad(const V3& xi, double* g) const {
     }
     for (int k = 0; k < N; ++k)
         for (int d = 0; d < 3; ++d) {
-            double s = 0.0;
+            real s = 0.0;
             for (int r = 0; r < N; ++r) s += coef[k * N + r] * dm[3 * r + d];
             g[3 * k + d] = s;
         }
@@ -190,21 +190,21 @@ void NodalBasis::grad(const V3& xi, double* g) const {
 
 TimeBasis::TimeBasis(int G_) : G(G_) {
     gauss_legendre01(G, nodes, weights);
-    std::vector<double> VT(G * G);
+    std::vector<real> VT(G * G);
     for (int a = 0; a < G; ++a)
         for (int r = 0; r < G; ++r) VT[r * G + a] = ipow(nodes[a], r);
     lu_inverse(G, VT);
     coef = VT;
 }
 
-double TimeBasis::eval(int a, double tau) const {
-    double s = 0.0;
+real TimeBasis::eval(int a, real tau) const {
+    real s = 0.0;
     for (int r = 0; r < G; ++r) s += coef[a * G + r] * ipow(tau, r);
     return s;
 }
 
-double TimeBasis::deriv(int a, double tau) const {
-    double s = 0.0;
+real TimeBasis::deriv(int a, real tau) const {
+    real s = 0.0;
     for (int r = 1; r < G; ++r) s += coef[a * G + r] * r * ipow(tau, r - 1);
     return s;
 }
@@ -215,7 +215,7 @@ Affine::Affine(const std::array<V3, 4>& v) {
         for (int r = 0; r < 3; ++r) J[r * 3 + c] = v[c + 1][r] - v[0][r];
     det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
           J[2] * (J[3] * J[7] - J[4] * J[6]);
-    std::vector<double> A(J, J + 9);
+    std::vector<real> A(J, J + 9);
     lu_inverse(3, A);
     for (int i = 0; i < 9; ++i) Jinv[i] = A[i];
 }
@@ -233,9 +233,9 @@ V3 Affine::to_phys(const V3& xi) const {
             v0[2] + J[6] * xi[0] + J[7] * xi[1] + J[8] * xi[2]};
 }
 
-bool lu_inverse(int n, std::vector<double>& A) {
+bool lu_inverse(int n, std::vector<real>& A) {
     // Gauss-Jordan elimination with partial pivoting.
-    std::vector<double> I(n * n, 0.0);
+    std::vector<real> I(n * n, 0.0);
     for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
     for (int c = 0; c < n; ++c) {
         int piv = c;
@@ -247,14 +247,14 @@ bool lu_inverse(int n, std::vector<double>& A) {
                 std::swap(A[c * n + k], A[piv * n + k]);
                 std::swap(I[c * n + k], I[piv * n + k]);
             }
-        double inv = 1.0 / A[c * n + c];
+        real inv = 1.0 / A[c * n + c];
         for (int k = 0; k < n; ++k) {
             A[c * n + k] *= inv;
             I[c * n + k] *= inv;
         }
         for (int r = 0; r < n; ++r) {
             if (r == c) continue;
-            double f = A[r * n + c];
+            real f = A[r * n + c];
             if (f == 0.0) continue;
             for (int k = 0; k < n; ++k) {
                 A[r * n + k] -= f * A[c * n + k];
@@ -266,15 +266,15 @@ bool lu_inverse(int n, std::vector<double>& A) {
     return true;
 }
 
-bool cholesky(int n, std::vector<double>& A) {
+bool cholesky(int n, std::vector<real>& A) {
     for (int j = 0; j < n; ++j) {
-        double s = A[j * n + j];
+        real s = A[j * n + j];
         for (int k = 0; k < j; ++k) s -= A[j * n + k] * A[j * n + k];
         if (!(s > 0.0)) return false;
-        double l = std::sqrt(s);
+        real l = std::sqrt(s);
         A[j * n + j] = l;
         for (int i = j + 1; i < n; ++i) {
-            double t = A[i * n + j];
+            real t = A[i * n + j];
             for (int k = 0; k < j; ++k) t -= A[i * n + k] * A[j * n + k];
             A[i * n + j] = t / l;
         }
@@ -283,17 +283,17 @@ bool cholesky(int n, std::vector<double>& A) {
     return true;
 }
 
-void cholesky_solve(int n, const std::vector<double>& L, double* b, int nrhs, int ldb) {
+void cholesky_solve(int n, const std::vector<real>& L, real* b, int nrhs, int ldb) {
     for (int c = 0; c < nrhs; ++c) {
         // forward: L y = b
         for (int i = 0; i < n; ++i) {
-            double s = b[i * ldb + c];
+            real s = b[i * ldb + c];
             for (int k = 0; k < i; ++k) s -= L[i * n + k] * b[k * ldb + c];
             b[i * ldb + c] = s / L[i * n + i];
         }
         // backward: L^T x = y
         for (int i = n - 1; i >= 0; --i) {
-            double s = b[i * ldb + c];
+            real s = b[i * ldb + c];
             for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * b[k * ldb + c];
             b[i * ldb + c] = s / L[i * n + i];
         }

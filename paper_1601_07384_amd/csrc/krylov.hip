@@ -560,45 +560,60 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
     const double bnorm = std::sqrt(bn2);
     int status = STDG_OK, inner_total = 0, outer = 0;
     double rel = 0.0;
+    // shift x to x_anchor = 0, set q = S x, r = b~ - S x (consistent residual)
+    // and return the anchored relative residual ||b_a - S_a x|| / ||b_a||.
+    auto check = [&](double& out) -> int {
+        hipLaunchKernelGGL(k_read_anchor, dim3(1), dim3(64), 0, c.s, x, c.scal + S_ANCH, m->anchor, m->anchor_node, G, N);
+        hipLaunchKernelGGL(k_shift, dim3(gb), dim3(256), 0, c.s, x, c.scal + S_ANCH, m->E, G, N);
+        CK(launch_apply_f64(m, x, w.q, c.s)); c.applies++;
+        hipLaunchKernelGGL((k_resid<double, double>), dim3(NBLK), dim3(RT), 0, c.s, w.z, w.q, w.r, n, c.partial);
+        hipLaunchKernelGGL(k_anch_res, dim3(NBLK), dim3(RT), 0, c.s, b, w.q, m->anchor, m->anchor_node, m->E, G, N,
+                           c.partial + NBLK);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial + NBLK, NBLK, c.scal, (int)S_RN2, (int)FIN_STORE);
+        CK(hipGetLastError());
+        double rn2;
+        if (int e = read_scal(c, S_RN2, rn2)) return e;
+        out = std::sqrt(rn2) / bnorm;
+        if (!std::isfinite(out)) { set_error("non-finite residual"); return STDG_ERR_NUMERIC; }
+        return STDG_OK;
+    };
     if (bnorm == 0.0) {
         hipLaunchKernelGGL(k_fill<double>, dim3(gb), dim3(256), 0, c.s, x, 0.0, n);
     } else if (!ir) {
         int it = 0;
-        double res = 0.0;
+        double res = 0.0, tol_abs = o.rtol * bnorm;
         outer = 1;
         // the recursive residual may drift from the true one: restart from the
-        // true residual until the true anchored residual meets the tolerance
-        for (int round = 0; round < 5; ++round) {
-            int left = o.max_iter - inner_total;
+        // true residual (with a tighter target) until the anchored residual
+        // meets the tolerance
+        for (int round = 0; round < 6; ++round) {
+            const int left = o.max_iter - inner_total;
             if (left <= 0) { status = STDG_NOT_CONVERGED; break; }
-            status = run_krylov<double>(c, o.method, w.z, x, w.r, w.p, w.q, w.V, mres, o.rtol * bnorm,
-                                        left, o.check_every, it, res);
+            status = run_krylov<double>(c, o.method, w.z, x, w.r, w.p, w.q, w.V, mres, tol_abs, left,
+                                        o.check_every, it, res);
             inner_total += it;
             if (status < 0) return status;
-            CK(launch_apply_f64(m, x, w.q, c.s)); c.applies++;
-            hipLaunchKernelGGL((k_resid<double, double>), dim3(NBLK), dim3(RT), 0, c.s, w.z, w.q, w.r, n, c.partial);
-            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_RN2, (int)FIN_STORE);
-            double rn2;
-            if (int e = read_scal(c, S_RN2, rn2)) return e;
-            if (std::sqrt(rn2) <= o.rtol * bnorm || status == STDG_NOT_CONVERGED) break;
+            if (int e = check(rel)) return e;
+            if (rel <= o.rtol) { status = STDG_OK; break; }
+            if (status == STDG_NOT_CONVERGED) break;
+            tol_abs *= 0.25;
         }
     } else {
         // FP64 iterative refinement around FP32 Krylov solves
-        for (outer = 1; outer <= o.max_outer; ++outer) {
-            CK(launch_apply_f64(m, x, w.q, c.s)); c.applies++;
-            hipLaunchKernelGGL((k_resid<double, double>), dim3(NBLK), dim3(RT), 0, c.s, w.z, w.q, w.r, n, c.partial);
-            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_RN2, (int)FIN_STORE);
-            double rn2;
-            if (int e = read_scal(c, S_RN2, rn2)) return e;
-            if (!std::isfinite(rn2)) { set_error("non-finite residual in refinement"); return STDG_ERR_NUMERIC; }
-            const double rn = std::sqrt(rn2);
-            if (rn <= o.rtol * bnorm) break;
-            if (inner_total >= o.max_iter) { status = STDG_NOT_CONVERGED; break; }
-            // inner right-hand side: r projected on the range of S, in FP32
+        for (outer = 1; outer <= o.max_outer + 1; ++outer) {
+            if (int e = check(rel)) return e;
+            if (rel <= o.rtol) { status = STDG_OK; break; }
+            if (outer > o.max_outer || inner_total >= o.max_iter) { status = STDG_NOT_CONVERGED; break; }
+            // inner right-hand side: the consistent residual projected on the
+            // range of S (per-time-node mean removed), in FP32
             if (int e = time_sums(c, w.r)) return e;
             hipLaunchKernelGGL(k_remove_mean<double>, dim3(gb), dim3(256), 0, c.s, w.r, c.scal + S_TIME, m->E, G, N);
+            hipLaunchKernelGGL((k_dot<double, double>), dim3(NBLK), dim3(RT), 0, c.s, w.r, w.r, n, c.partial);
+            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_NORM, (int)FIN_SQRT);
             CK(convert_d2f(w.r, w.b32, n, c.s));
             hipLaunchKernelGGL(k_fill<float>, dim3(gb), dim3(256), 0, c.s, w.x32, 0.0f, n);
+            double rn;
+            if (int e = read_scal(c, S_NORM, rn)) return e;
             int it = 0;
             double res = 0.0;
             status = run_krylov<float>(c, o.method, w.b32, w.x32, w.r32, w.p32, w.q32, w.V32, mres,
@@ -607,24 +622,10 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
             if (status < 0) return status;
             hipLaunchKernelGGL(k_add_f32, dim3(gb), dim3(256), 0, c.s, x, w.x32, n);
             CK(hipGetLastError());
-            status = STDG_OK;
         }
-        if (outer > o.max_outer) status = STDG_NOT_CONVERGED;
-    }
-    // shift so that x_anchor = 0 at every time node, then the exact anchored residual
-    hipLaunchKernelGGL(k_read_anchor, dim3(1), dim3(64), 0, c.s, x, c.scal + S_ANCH, m->anchor, m->anchor_node, G, N);
-    hipLaunchKernelGGL(k_shift, dim3(gb), dim3(256), 0, c.s, x, c.scal + S_ANCH, m->E, G, N);
-    CK(launch_apply_f64(m, x, w.q, c.s)); c.applies++;
-    hipLaunchKernelGGL(k_anch_res, dim3(NBLK), dim3(RT), 0, c.s, b, w.q, m->anchor, m->anchor_node, m->E, G, N, c.partial);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_RN2, (int)FIN_STORE);
-    double rn2 = 0.0;
-    if (bnorm > 0.0) {
-        if (int e = read_scal(c, S_RN2, rn2)) return e;
-        rel = std::sqrt(rn2) / bnorm;
+        outer = std::min(outer, o.max_outer);
     }
     CK(hipStreamSynchronize(c.s));
-    if (!std::isfinite(rel)) { set_error("non-finite final residual"); status = STDG_ERR_NUMERIC; }
-    if (status == STDG_OK && rel > o.rtol * 1.0000001) status = STDG_NOT_CONVERGED;
     if (rep) {
         rep->status = status;
         rep->outer_iters = outer;

@@ -63,12 +63,12 @@ V3 centroid(const std::array<V3, 4>& v) {
 }
 
 // Taylor monomials (x - x0)^k / h^|k| (eq. bf_2), exponents first-fastest.
-void taylor_eval(const std::vector<std::array<int, 3>>& ex, const V3& x, const V3& x0, double h,
-                 double* out) {
-    double y[3] = {(x[0] - x0[0]) / h, (x[1] - x0[1]) / h, (x[2] - x0[2]) / h};
+void taylor_eval(const std::vector<std::array<int, 3>>& ex, const V3& x, const V3& x0, real h,
+                 real* out) {
+    real y[3] = {(x[0] - x0[0]) / h, (x[1] - x0[1]) / h, (x[2] - x0[2]) / h};
     int p = 0;
     for (auto& e : ex) p = std::max(p, e[0] + e[1] + e[2]);
-    double pw[3][8];
+    real pw[3][8];
     for (int d = 0; d < 3; ++d) {
         pw[d][0] = 1.0;
         for (int k = 1; k <= p; ++k) pw[d][k] = pw[d][k - 1] * y[d];
@@ -82,8 +82,8 @@ void taylor_eval(const std::vector<std::array<int, 3>>& ex, const V3& x, const V
 // neighbour (side 1): the spatial Q blocks (3 x N x N, rows = dual basis) of
 // both sides and the dual mass matrix M^sp_j.
 struct DualFaceBlocks {
-    std::vector<double> M;          // N x N
-    std::vector<double> Q[2];       // 3 x N x N each
+    std::vector<real> M;          // N x N
+    std::vector<real> Q[2];       // 3 x N x N each
 };
 
 static void dual_face_blocks(const NodalBasis& phi, int p, const std::array<V3, 4>& Vt, int f,
@@ -94,8 +94,8 @@ static void dual_face_blocks(const NodalBasis& phi, int p, const std::array<V3, 
     for (int k = 0, m = 0; k < 4; ++k)
         if (k != f) P[m++] = Vt[k];
     const V3 bc[2] = {centroid(Vt), centroid(Vk)};
-    // dual basis centre: volume centroid of H_j; scale: its diameter
-    double vol[2];
+    // dual basis centre: volume centroid of H_j; scale: half its diameter
+    real vol[2];
     V3 cen[2];
     for (int s = 0; s < 2; ++s) {
         vol[s] = std::fabs(det3(sub(P[0], bc[s]), sub(P[1], bc[s]), sub(P[2], bc[s]))) / 6.0;
@@ -103,9 +103,9 @@ static void dual_face_blocks(const NodalBasis& phi, int p, const std::array<V3, 
     }
     V3 x0 = scale(add(scale(cen[0], vol[0]), scale(cen[1], vol[1])), 1.0 / (vol[0] + vol[1]));
     V3 pts5[5] = {P[0], P[1], P[2], bc[0], bc[1]};
-    double h = 0.0;
+    real h = 0.0;   // half the diameter: scaled coordinates in [-1, 1]
     for (int a = 0; a < 5; ++a)
-        for (int b = a + 1; b < 5; ++b) h = std::max(h, norm(sub(pts5[a], pts5[b])));
+        for (int b = a + 1; b < 5; ++b) h = std::max(h, 0.5 * norm(sub(pts5[a], pts5[b])));
     V3 nrm = cross(sub(P[1], P[0]), sub(P[2], P[0]));
     nrm = scale(nrm, 1.0 / norm(nrm));
     if (dot(nrm, sub(P[0], bc[0])) < 0) nrm = scale(nrm, -1.0);   // outward of t
@@ -115,15 +115,15 @@ static void dual_face_blocks(const NodalBasis& phi, int p, const std::array<V3, 
     const Affine A[2] = {Affine(Vt), Affine(Vk)};
     const int q = p + 1;
     const Rule tr = tet_rule(q);
-    std::vector<double> ps(N), ph(N), gr(3 * N), gx(3 * N);
+    std::vector<real> ps(N), ph(N), gr(3 * N), gx(3 * N);
     for (int s = 0; s < 2; ++s) {
         // sub-tetrahedron T_{i,j}: the face and the element's barycentre
         std::array<V3, 4> sv = {bc[s], P[0], P[1], P[2]};
         Affine sa(sv);
-        const double jac = std::fabs(sa.det);
+        const real jac = std::fabs(sa.det);
         for (size_t m = 0; m < tr.w.size(); ++m) {
             V3 x = sa.to_phys(tr.pts[m]);
-            double w = tr.w[m] * jac;
+            real w = tr.w[m] * jac;
             taylor_eval(ex, x, x0, h, ps.data());
             V3 xi = A[s].to_ref(x);
             phi.grad(xi, gr.data());
@@ -134,7 +134,7 @@ static void dual_face_blocks(const NodalBasis& phi, int p, const std::array<V3, 
                                     A[s].Jinv[1 * 3 + d] * gr[3 * k + 1] +
                                     A[s].Jinv[2 * 3 + d] * gr[3 * k + 2];
             for (int a = 0; a < N; ++a) {
-                const double wa = w * ps[a];
+                const real wa = w * ps[a];
                 for (int b = 0; b < N; ++b) out.M[a * N + b] += wa * ps[b];
                 for (int d = 0; d < 3; ++d)
                     for (int b = 0; b < N; ++b) out.Q[s][(d * N + a) * N + b] += wa * gx[3 * b + d];
@@ -144,17 +144,17 @@ static void dual_face_blocks(const NodalBasis& phi, int p, const std::array<V3, 
     // face part: - int_Gamma psi phi_i n_ij  (n_ij outward of element i)
     const Rule fr = tri_rule(q);
     const V3 e1 = sub(P[1], P[0]), e2 = sub(P[2], P[0]);
-    const double area2 = norm(cross(e1, e2));
+    const real area2 = norm(cross(e1, e2));
     for (size_t m = 0; m < fr.w.size(); ++m) {
         V3 x = add(P[0], add(scale(e1, fr.pts[m][0]), scale(e2, fr.pts[m][1])));
-        double w = fr.w[m] * area2;
+        real w = fr.w[m] * area2;
         taylor_eval(ex, x, x0, h, ps.data());
         for (int s = 0; s < 2; ++s) {
             phi.eval(A[s].to_ref(x), ph.data());
-            const double sg = (s == 0) ? 1.0 : -1.0;
+            const real sg = (s == 0) ? 1.0 : -1.0;
             for (int a = 0; a < N; ++a)
                 for (int d = 0; d < 3; ++d) {
-                    const double c = w * ps[a] * sg * nrm[d];
+                    const real c = w * ps[a] * sg * nrm[d];
                     for (int b = 0; b < N; ++b) out.Q[s][(d * N + a) * N + b] -= c * ph[b];
                 }
         }
@@ -165,12 +165,13 @@ static V3 neighbour_shift(const stdg_mesh* m, int64_t t, int f);
 
 // Five dt^2-scaled spatial blocks of element t: [0] diagonal, [1+f] coupling
 // to the neighbour across local face f (zero on a boundary face).
-static int element_blocks(const stdg_mesh* m, int64_t t, const NodalBasis& phi, double* B) {
+static int element_blocks(const stdg_mesh* m, int64_t t, const NodalBasis& phi, double* Bout) {
     const int N = m->N;
-    std::fill(B, B + 5 * N * N, 0.0);
-    const double dt2 = m->cfg.dt * m->cfg.dt;
+    std::vector<real> Bv(5 * N * N, 0.0L);
+    real* B = Bv.data();
+    const real dt2 = m->cfg.dt * m->cfg.dt;
     DualFaceBlocks fb;
-    std::vector<double> Z(3 * N * N);
+    std::vector<real> Z(3 * N * N);
     for (int f = 0; f < 4; ++f) {
         const int64_t k = m->nbr[t * 4 + f];
         if (k < 0) continue;
@@ -178,43 +179,43 @@ static int element_blocks(const stdg_mesh* m, int64_t t, const NodalBasis& phi, 
         std::array<V3, 4> Vk = m->vert[k];
         for (auto& v : Vk) v = add(v, sh);
         dual_face_blocks(phi, m->p, m->vert[t], f, Vk, fb);
-        std::vector<double> L = fb.M;
+        std::vector<real> L = fb.M;
         if (!cholesky(N, L)) return -1;
         for (int s = 0; s < 2; ++s) {
             // Z = M^-1 Q_s (per component)
             std::copy(fb.Q[s].begin(), fb.Q[s].end(), Z.begin());
             for (int d = 0; d < 3; ++d) cholesky_solve(N, L, Z.data() + d * N * N, N, N);
-            double* dst = B + (s == 0 ? 0 : (1 + f)) * N * N;
+            real* dst = B + (s == 0 ? 0 : (1 + f)) * N * N;
             for (int d = 0; d < 3; ++d)
                 for (int a = 0; a < N; ++a)
                     for (int c = 0; c < N; ++c) {
-                        const double qa = fb.Q[0][(d * N + c) * N + a];   // (Q_t^T)_{a c}
+                        const real qa = fb.Q[0][(d * N + c) * N + a];   // (Q_t^T)_{a c}
                         if (qa == 0.0) continue;
                         for (int b = 0; b < N; ++b) dst[a * N + b] += qa * Z[(d * N + c) * N + b];
                     }
         }
     }
-    for (int i = 0; i < 5 * N * N; ++i) B[i] *= dt2;
+    for (int i = 0; i < 5 * N * N; ++i) Bout[i] = (double)(B[i] * dt2);
     return 0;
 }
 
-static void time_factor(int G, std::vector<double>& C) {
+static void time_factor(int G, std::vector<double>& Cout) {
     TimeBasis tb(G);
-    std::vector<double> T(G * G), W(G);
-    std::vector<double> xq, wq;
+    std::vector<real> T(G * G), W(G);
+    std::vector<real> xq, wq;
     gauss_legendre01(G + 1, xq, wq);
     for (int a = 0; a < G; ++a) {
         W[a] = tb.weights[a];
         for (int b = 0; b < G; ++b) {
-            double s = 0.0;
+            real s = 0.0;
             for (size_t m = 0; m < xq.size(); ++m) s += wq[m] * tb.deriv(a, xq[m]) * tb.eval(b, xq[m]);
             T[a * G + b] = tb.eval(a, 1.0) * tb.eval(b, 1.0) - s;
         }
     }
     lu_inverse(G, T);
-    C.assign(G * G, 0.0);
+    Cout.assign(G * G, 0.0);
     for (int a = 0; a < G; ++a)
-        for (int b = 0; b < G; ++b) C[a * G + b] = W[a] * T[a * G + b] * W[b];
+        for (int b = 0; b < G; ++b) Cout[a * G + b] = (double)(W[a] * T[a * G + b] * W[b]);
 }
 
 int build_topology(stdg_mesh* m, const double* xyz, int64_t n_vert, const int64_t* tets) {
@@ -226,10 +227,10 @@ int build_topology(stdg_mesh* m, const double* xyz, int64_t n_vert, const int64_
     V3 lo = {1e300, 1e300, 1e300}, hi = {-1e300, -1e300, -1e300};
     for (int64_t v = 0; v < n_vert; ++v)
         for (int d = 0; d < 3; ++d) {
-            lo[d] = std::min(lo[d], xyz[3 * v + d]);
-            hi[d] = std::max(hi[d], xyz[3 * v + d]);
+            lo[d] = std::min(lo[d], (real)xyz[3 * v + d]);
+            hi[d] = std::max(hi[d], (real)xyz[3 * v + d]);
         }
-    const double diag = norm(sub(hi, lo));
+    const real diag = norm(sub(hi, lo));
     m->perm.resize(E);
     std::iota(m->perm.begin(), m->perm.end(), 0);
     if (cfg.reorder) {
@@ -254,7 +255,7 @@ int build_topology(stdg_mesh* m, const double* xyz, int64_t n_vert, const int64_
     m->iperm.resize(E);
     for (int64_t t = 0; t < E; ++t) m->iperm[m->perm[t]] = t;
     m->vert.resize(E);
-    double min_edge = 1e300;
+    real min_edge = 1e300;
     for (int64_t t = 0; t < E; ++t) {
         const int64_t* tv = tets + 4 * m->perm[t];
         for (int k = 0; k < 4; ++k) {
@@ -364,10 +365,10 @@ int build_blocks(stdg_mesh* m) {
     const int64_t E = m->E;
     const int N = m->N;
     // geometric class keys
-    double hmin = 1e300;
+    real hmin = 1e300;
     for (int64_t t = 0; t < E; ++t)
         for (int a = 1; a < 4; ++a) hmin = std::min(hmin, norm(sub(m->vert[t][a], m->vert[t][0])));
-    const double quantum = 1e-7 * hmin;
+    const real quantum = 1e-7 * hmin;
     std::map<std::vector<int64_t>, int> classes;
     std::vector<int64_t> rep;
     m->cls.resize(E);
