@@ -2,37 +2,200 @@
 //
 // S = dt^2 S^sp (x) C: for element i with neighbours k_f across its local
 // faces f,
-//   Y_i = sum_{k in {i, k_0..k_3}} B_{c(i),k} X_k C^T
+//   Y_i = sum_{k in {i, k_0..k_3}} B_{c(i),k} (X_k C^T)
 // where X_k is the N x G coefficient matrix of element k ([G][N] in memory),
 // B_{c,0..4} the class-deduplicated dt^2-scaled spatial blocks and C the G x G
-// time factor.  One thread produces one spatial row n of one element for all
-// G time nodes; neighbour coefficients are gathered through the neighbour
-// table (elements are numbered along a Hilbert curve, so the four neighbours
-// of a tile are mostly inside or next to it).
+// time factor.
+//
+// Work decomposition: one thread per (element, time node a).  The thread
+// forms the time-mixed neighbour column x'_m = sum_b C_ab x_k[b][m] on the fly
+// and accumulates its N outputs y_i[a][.] in registers.  Elements are ordered
+// so that every full wavefront holds 64 elements of one class (Hilbert order
+// within each class): the wavefront's block B_{c,k} is then uniform and is
+// read through scalar loads (one broadcast per column, stored transposed
+// BT[c][k][m][r] so a column is contiguous), and the FP64 FMAs take it as a
+// scalar operand.  Wavefronts that mix classes (the tail, or meshes without
+// repeated geometry) take the same loop with per-lane block loads.
 #include "internal.hpp"
 #include "kernels.hpp"
 
 namespace stdg {
 
+template <int N, int G, typename T>
+__device__ __forceinline__ void accumulate_block(const T* __restrict__ Bk, const T* __restrict__ xt,
+                                                 const T (&Ca)[G], T (&acc)[N]) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        T xp = T(0);
+#pragma unroll
+        for (int b = 0; b < G; ++b) xp += Ca[b] * xt[b * N + m];
+        const T* col = Bk + m * N;
+#pragma unroll
+        for (int r = 0; r < N; ++r) acc[r] += col[r] * xp;
+    }
+}
+
+template <int N, int G, typename T>
+__global__ void __launch_bounds__(256) schur_apply_tn(
+    const T* __restrict__ BT, const int32_t* __restrict__ cls, const int32_t* __restrict__ nbr,
+    const T* __restrict__ C, const T* __restrict__ x, T* __restrict__ y, int64_t E) {
+    const int a = (int)(blockIdx.x % G);
+    const int64_t i = (int64_t)(blockIdx.x / G) * 256 + threadIdx.x;
+    const bool valid = i < E;
+    const int64_t ii = valid ? i : E - 1;          // inactive lanes mirror a valid element
+    const int c = cls[ii];
+    const int c0 = __builtin_amdgcn_readfirstlane(c);
+    const bool uniform = __all(c == c0);
+    T Ca[G];
+#pragma unroll
+    for (int b = 0; b < G; ++b) Ca[b] = C[a * G + b];
+    T acc[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) acc[r] = T(0);
+    int nb[5];
+    nb[0] = (int)ii;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) nb[f + 1] = nbr[4 * ii + f];
+    if (uniform) {
+        const T* Bc = BT + (int64_t)c0 * 5 * N * N;
+        for (int k = 0; k < 5; ++k) {
+            const int t = nb[k];
+            // a uniform class has the same boundary faces on every lane
+            if (__builtin_amdgcn_readfirstlane(t) < 0) continue;
+            accumulate_block<N, G, T>(Bc + k * N * N, x + (int64_t)t * G * N, Ca, acc);
+        }
+    } else {
+        const T* Bc = BT + (int64_t)c * 5 * N * N;
+        for (int k = 0; k < 5; ++k) {
+            const int t = nb[k];
+            if (t < 0) continue;
+            accumulate_block<N, G, T>(Bc + k * N * N, x + (int64_t)t * G * N, Ca, acc);
+        }
+    }
+    if (valid) {
+        T* yi = y + (i * G + a) * N;
+#pragma unroll
+        for (int r = 0; r < N; ++r) yi[r] = acc[r];
+    }
+}
+
+// Copy the 64 time-mixed rows x'[lane'] = sum_b C_ab x[nb(lane')][b][.] of a
+// wavefront into its panel: 64/N rows per instruction group, consecutive
+// lanes on consecutive spatial values, G loads per value.
+template <int N, int G, int RS, typename T>
+__device__ __forceinline__ void load_panel(T* __restrict__ panel, const T* __restrict__ x, int t,
+                                           const T (&Ca)[G], int roff, int col0) {
+    constexpr int RPI = 64 / N;
+#pragma unroll
+    for (int j0 = 0; j0 < 64; j0 += RPI) {
+        const int row = j0 + roff;
+        const int tr = __shfl(t, row < 64 ? row : 63, 64);
+        if (roff < RPI && row < 64) {
+            T v = T(0);
+            if (tr >= 0) {
+                const T* xt = x + (int64_t)tr * G * N + col0;
+#pragma unroll
+                for (int b = 0; b < G; ++b) v += Ca[b] * xt[b * N];
+            }
+            panel[row * RS + col0] = v;
+        }
+    }
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void panel_fma(const T* __restrict__ Bk, const T* __restrict__ xr,
+                                          T (&acc)[N]) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const T xp = xr[m];
+        const T* col = Bk + m * N;
+#pragma unroll
+        for (int r = 0; r < N; ++r) acc[r] += col[r] * xp;
+    }
+}
+
+// Panel-staged kernel.  A block of 256 threads holds four wavefronts; each
+// wavefront owns 64 elements, one time node a and a private LDS panel.  For
+// each of the five couplings k the wavefront first copies the 64 time-mixed
+// neighbour rows into its panel (a few cache lines per load instruction
+// instead of one line per lane), then every lane runs the N x N block against
+// its own row: panel values from LDS (odd row stride), block columns from
+// scalar registers when the wavefront holds one class.  Boundary faces load
+// zero rows instead of being skipped, so every wavefront reaches every barrier.
+template <int N, int G, typename T>
+__global__ void __launch_bounds__(256) schur_apply_lds(
+    const T* __restrict__ BT, const int32_t* __restrict__ cls, const int32_t* __restrict__ nbr,
+    const T* __restrict__ C, const T* __restrict__ x, T* __restrict__ y, int64_t E) {
+    static_assert(N <= 64, "panel rows longer than a wavefront");
+    constexpr int RS = N | 1;                     // odd row stride (elements)
+    __shared__ T panels[4 * 64 * RS];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    T* panel = panels + wave * 64 * RS;
+    const int a = (int)(blockIdx.x % G);
+    const int64_t i = (int64_t)(blockIdx.x / G) * 256 + threadIdx.x;
+    const bool valid = i < E;
+    const int64_t ii = valid ? i : E - 1;
+    const int c = cls[ii];
+    const int c0 = __builtin_amdgcn_readfirstlane(c);
+    const bool uniform = __all(c == c0);
+    T Ca[G];
+#pragma unroll
+    for (int b = 0; b < G; ++b) Ca[b] = C[a * G + b];
+    T acc[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) acc[r] = T(0);
+    int nb[5];
+    nb[0] = (int)ii;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) nb[f + 1] = nbr[4 * ii + f];
+    const int roff = lane / N;                    // this lane's row within a copy group
+    const int col0 = lane - roff * N;
+    const T* xr = panel + lane * RS;
+    if (uniform) {
+        // one class for the whole wavefront: block columns through scalar loads
+        const T* Bc = BT + (int64_t)c0 * 5 * N * N;
+        for (int k = 0; k < 5; ++k) {
+            load_panel<N, G, RS, T>(panel, x, nb[k], Ca, roff, col0);
+            __syncthreads();
+            panel_fma<N, T>(Bc + k * N * N, xr, acc);
+            __syncthreads();
+        }
+    } else {
+        const T* Bc = BT + (int64_t)c * 5 * N * N;
+        for (int k = 0; k < 5; ++k) {
+            load_panel<N, G, RS, T>(panel, x, nb[k], Ca, roff, col0);
+            __syncthreads();
+            panel_fma<N, T>(Bc + k * N * N, xr, acc);
+            __syncthreads();
+        }
+    }
+    if (valid) {
+        T* yi = y + (i * G + a) * N;
+#pragma unroll
+        for (int r = 0; r < N; ++r) yi[r] = acc[r];
+    }
+}
+
+// Any (N, G): one thread per (element, spatial row), all time nodes.
 template <int G, typename T>
 __global__ void __launch_bounds__(256) schur_apply_rows(
-    const T* __restrict__ B, const int32_t* __restrict__ cls, const int32_t* __restrict__ nbr,
+    const T* __restrict__ BT, const int32_t* __restrict__ cls, const int32_t* __restrict__ nbr,
     const T* __restrict__ C, const T* __restrict__ x, T* __restrict__ y, int64_t E, int N) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = gid / N;
     const int n = (int)(gid - i * N);
     if (i >= E) return;
-    const T* Bc = B + (int64_t)cls[i] * 5 * N * N;
+    const T* Bc = BT + (int64_t)cls[i] * 5 * N * N;
     T acc[G];
 #pragma unroll
     for (int b = 0; b < G; ++b) acc[b] = T(0);
     for (int k = 0; k < 5; ++k) {
         const int64_t t = (k == 0) ? i : (int64_t)nbr[4 * i + (k - 1)];
         if (t < 0) continue;
-        const T* Br = Bc + ((int64_t)k * N + n) * N;
         const T* xt = x + t * G * N;
         for (int m = 0; m < N; ++m) {
-            const T bv = Br[m];
+            const T bv = Bc[((int64_t)k * N + m) * N + n];
 #pragma unroll
             for (int b = 0; b < G; ++b) acc[b] += bv * xt[b * N + m];
         }
@@ -47,8 +210,16 @@ __global__ void __launch_bounds__(256) schur_apply_rows(
     }
 }
 
+template <int N, int G, typename T>
+static hipError_t launch_tn(const stdg_mesh* m, const T* BT, const T* C, const T* x, T* y, hipStream_t s) {
+    const int64_t blocks = (m->E + 255) / 256 * G;
+    hipLaunchKernelGGL((schur_apply_tn<N, G, T>), dim3((unsigned)blocks), dim3(256), 0, s, BT,
+                       m->d.cls, m->d.nbr, C, x, y, m->E);
+    return hipGetLastError();
+}
+
 template <typename T>
-static hipError_t launch_rows(const stdg_mesh* m, const T* B, const T* C, const T* x, T* y,
+static hipError_t launch_rows(const stdg_mesh* m, const T* BT, const T* C, const T* x, T* y,
                               hipStream_t s) {
     const int64_t work = m->E * m->N;
     const int threads = 256;
@@ -56,7 +227,7 @@ static hipError_t launch_rows(const stdg_mesh* m, const T* B, const T* C, const 
     switch (m->G) {
 #define STDG_G(g)                                                                              \
     case g:                                                                                    \
-        hipLaunchKernelGGL((schur_apply_rows<g, T>), dim3(blocks), dim3(threads), 0, s, B,    \
+        hipLaunchKernelGGL((schur_apply_rows<g, T>), dim3(blocks), dim3(threads), 0, s, BT,   \
                            m->d.cls, m->d.nbr, C, x, y, m->E, m->N);                          \
         break;
         STDG_G(1) STDG_G(2) STDG_G(3) STDG_G(4) STDG_G(5) STDG_G(6) STDG_G(7)
@@ -67,15 +238,46 @@ static hipError_t launch_rows(const stdg_mesh* m, const T* B, const T* C, const 
     return hipGetLastError();
 }
 
+template <int N, int G, typename T>
+static hipError_t launch_lds(const stdg_mesh* m, const T* BT, const T* C, const T* x, T* y, hipStream_t s) {
+    const int64_t blocks = (m->E + 255) / 256 * G;
+    hipLaunchKernelGGL((schur_apply_lds<N, G, T>), dim3((unsigned)blocks), dim3(256), 0, s, BT,
+                       m->d.cls, m->d.nbr, C, x, y, m->E);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_apply(const stdg_mesh* m, const T* BT, const T* C, const T* x, T* y,
+                               hipStream_t s) {
+    // Measured on MI355X (FP64): the panel-staged kernel wins for several time
+    // nodes with N >= 20 (N=20,G=2: 92 vs 116 us; N=35,G=5: 364 vs 464 us on
+    // the 82,944 / 24,576-element meshes), the direct-gather kernel elsewhere
+    // and for FP32 everywhere.
+    if (sizeof(T) == 8 && m->G >= 2) {
+#define STDG_NG(n, g) \
+    if (m->N == n && m->G == g) return launch_lds<n, g, T>(m, BT, C, x, y, s);
+        STDG_NG(20, 2) STDG_NG(20, 3) STDG_NG(20, 4) STDG_NG(20, 5)
+        STDG_NG(35, 2) STDG_NG(35, 3) STDG_NG(35, 4) STDG_NG(35, 5)
+#undef STDG_NG
+    }
+#define STDG_NG(n, g) \
+    if (m->N == n && m->G == g) return launch_tn<n, g, T>(m, BT, C, x, y, s);
+    STDG_NG(4, 1) STDG_NG(4, 2) STDG_NG(4, 3) STDG_NG(4, 4) STDG_NG(4, 5)
+    STDG_NG(10, 1) STDG_NG(10, 2) STDG_NG(10, 3) STDG_NG(10, 4) STDG_NG(10, 5)
+    STDG_NG(20, 1) STDG_NG(20, 2) STDG_NG(20, 3) STDG_NG(20, 4) STDG_NG(20, 5)
+    STDG_NG(35, 1) STDG_NG(35, 2) STDG_NG(35, 3) STDG_NG(35, 4) STDG_NG(35, 5)
+#undef STDG_NG
+    return launch_rows<T>(m, BT, C, x, y, s);
+}
+
 hipError_t launch_apply_f64(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
-    return launch_rows<double>(m, m->d.blocks, m->d.C, x, y, s);
+    return launch_apply<double>(m, m->d.blocks, m->d.C, x, y, s);
 }
 
 hipError_t launch_apply_f32(const stdg_mesh* m, const float* x, float* y, hipStream_t s) {
-    return launch_rows<float>(m, m->d.blocks32, m->d.C32, x, y, s);
+    return launch_apply<float>(m, m->d.blocks32, m->d.C32, x, y, s);
 }
 
-// FP32 blocks with FP64 input/output: convert through a scratch vector.
 __global__ void cvt_d2f(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = (float)a[i];

@@ -16,9 +16,18 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 void free_workspace(stdg_mesh* m);
 
 int upload_tables(stdg_mesh* m) {
-    const size_t nb = (size_t)m->n_classes * 5 * m->N * m->N;
+    // device layout: each N x N block transposed (BT[c][k][m][r] = B[c][k][r][m])
+    const int N = m->N;
+    const size_t nb = (size_t)m->n_classes * 5 * N * N;
+    std::vector<double> bt(nb);
     std::vector<float> b32(nb);
-    for (size_t i = 0; i < nb; ++i) b32[i] = (float)m->blocks[i];
+    for (size_t blk = 0; blk < (size_t)m->n_classes * 5; ++blk)
+        for (int r = 0; r < N; ++r)
+            for (int c = 0; c < N; ++c) {
+                const double v = m->blocks[blk * N * N + (size_t)r * N + c];
+                bt[blk * N * N + (size_t)c * N + r] = v;
+                b32[blk * N * N + (size_t)c * N + r] = (float)v;
+            }
     std::vector<float> c32(m->Ctime.begin(), m->Ctime.end());
     std::vector<int32_t> cls(m->cls.begin(), m->cls.end());
     STDG_HIP(hipMalloc(&m->d.blocks, nb * sizeof(double)));
@@ -27,7 +36,7 @@ int upload_tables(stdg_mesh* m) {
     STDG_HIP(hipMalloc(&m->d.nbr, 4 * m->E * sizeof(int32_t)));
     STDG_HIP(hipMalloc(&m->d.C, m->G * m->G * sizeof(double)));
     STDG_HIP(hipMalloc(&m->d.C32, m->G * m->G * sizeof(float)));
-    STDG_HIP(hipMemcpy(m->d.blocks, m->blocks.data(), nb * sizeof(double), hipMemcpyHostToDevice));
+    STDG_HIP(hipMemcpy(m->d.blocks, bt.data(), nb * sizeof(double), hipMemcpyHostToDevice));
     STDG_HIP(hipMemcpy(m->d.blocks32, b32.data(), nb * sizeof(float), hipMemcpyHostToDevice));
     STDG_HIP(hipMemcpy(m->d.cls, cls.data(), m->E * sizeof(int32_t), hipMemcpyHostToDevice));
     STDG_HIP(hipMemcpy(m->d.nbr, m->nbr.data(), 4 * m->E * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -74,8 +83,15 @@ static int mesh_build_impl(const double* xyz, int64_t n_vert, const int64_t* tet
         m->N = N;
         m->Nst = N * m->G;
         m->E = n_tet;
-        int e = build_topology(m, xyz, n_vert, tets);
-        if (e == STDG_OK) e = build_blocks(m);
+        std::vector<int64_t> rep;
+        int e = build_topology(m, xyz, n_vert, tets, nullptr);
+        if (e == STDG_OK) e = assign_classes(m, rep);
+        if (e == STDG_OK && cfg->reorder) {
+            const std::vector<int64_t> order = class_chunk_order(m);
+            e = build_topology(m, xyz, n_vert, tets, &order);
+            if (e == STDG_OK) e = assign_classes(m, rep);
+        }
+        if (e == STDG_OK) e = build_blocks(m, rep);
         if (e == STDG_OK) {
             m->anchor = m->iperm[cfg->anchor_tet];
             m->anchor_node = cfg->anchor_node;

@@ -3,6 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+#include <vector>
+
 struct stdg_mesh;
 
 namespace stdg {
@@ -12,8 +15,11 @@ hipError_t launch_apply_f32(const stdg_mesh* m, const float* x, float* y, hipStr
 hipError_t convert_d2f(const double* a, float* b, int64_t n, hipStream_t s);
 hipError_t convert_f2d(const float* a, double* b, int64_t n, hipStream_t s);
 
-int build_topology(stdg_mesh* m, const double* xyz, int64_t n_vert, const int64_t* tets);
-int build_blocks(stdg_mesh* m);
+int build_topology(stdg_mesh* m, const double* xyz, int64_t n_vert, const int64_t* tets,
+                   const std::vector<int64_t>* order);
+int assign_classes(stdg_mesh* m, std::vector<int64_t>& rep);
+std::vector<int64_t> class_chunk_order(const stdg_mesh* m);
+int build_blocks(stdg_mesh* m, const std::vector<int64_t>& rep);
 int upload_tables(stdg_mesh* m);
 void free_tables(stdg_mesh* m);
 

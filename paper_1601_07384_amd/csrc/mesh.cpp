@@ -218,7 +218,8 @@ static void time_factor(int G, std::vector<double>& Cout) {
         for (int b = 0; b < G; ++b) Cout[a * G + b] = (double)(W[a] * T[a * G + b] * W[b]);
 }
 
-int build_topology(stdg_mesh* m, const double* xyz, int64_t n_vert, const int64_t* tets) {
+int build_topology(stdg_mesh* m, const double* xyz, int64_t n_vert, const int64_t* tets,
+                   const std::vector<int64_t>* order) {
     const int64_t E = m->E;
     const stdg_config& cfg = m->cfg;
     for (int64_t i = 0; i < 4 * E; ++i)
@@ -233,7 +234,9 @@ int build_topology(stdg_mesh* m, const double* xyz, int64_t n_vert, const int64_
     const real diag = norm(sub(hi, lo));
     m->perm.resize(E);
     std::iota(m->perm.begin(), m->perm.end(), 0);
-    if (cfg.reorder) {
+    if (order) {
+        m->perm = *order;
+    } else if (cfg.reorder) {
         std::vector<uint64_t> key(E);
         const int bits = 16;
         const double span = (1u << bits) - 1;
@@ -361,16 +364,18 @@ static V3 neighbour_shift(const stdg_mesh* m, int64_t t, int f) {
     return scale(F.shift, -1.0);                           // neighbour is the left element
 }
 
-int build_blocks(stdg_mesh* m) {
+// Class of every element: elements whose own vertices and whose four
+// neighbours (in local vertex order, relative to local vertex 0, periodic
+// neighbours translated) coincide share their operator blocks.  rep[c] is
+// the first element of class c.
+int assign_classes(stdg_mesh* m, std::vector<int64_t>& rep) {
     const int64_t E = m->E;
-    const int N = m->N;
-    // geometric class keys
     real hmin = 1e300;
     for (int64_t t = 0; t < E; ++t)
         for (int a = 1; a < 4; ++a) hmin = std::min(hmin, norm(sub(m->vert[t][a], m->vert[t][0])));
     const real quantum = 1e-7 * hmin;
     std::map<std::vector<int64_t>, int> classes;
-    std::vector<int64_t> rep;
+    rep.clear();
     m->cls.resize(E);
     for (int64_t t = 0; t < E; ++t) {
         std::vector<int64_t> key;
@@ -395,6 +400,38 @@ int build_blocks(stdg_mesh* m) {
         m->cls[t] = it->second;
     }
     m->n_classes = (int)rep.size();
+    return STDG_OK;
+}
+
+// Element order for the operator kernels: the elements of each class in
+// Hilbert order, dealt out in chunks of 64 (one wavefront) round-robin over
+// the classes, so that every full wavefront holds a single class and the
+// chunks of all classes advance through space together; the partial
+// remainder of each class goes to the end so full chunks stay aligned.
+std::vector<int64_t> class_chunk_order(const stdg_mesh* m) {
+    const int W = 64;
+    std::vector<std::vector<int64_t>> lists(m->n_classes);
+    for (int64_t t = 0; t < m->E; ++t) lists[m->cls[t]].push_back(m->perm[t]);
+    std::vector<int64_t> order;
+    order.reserve(m->E);
+    std::vector<size_t> pos(m->n_classes, 0);
+    bool more = true;
+    while (more) {
+        more = false;
+        for (int c = 0; c < m->n_classes; ++c)
+            if (pos[c] + W <= lists[c].size()) {
+                order.insert(order.end(), lists[c].begin() + pos[c], lists[c].begin() + pos[c] + W);
+                pos[c] += W;
+                more = true;
+            }
+    }
+    for (int c = 0; c < m->n_classes; ++c)
+        order.insert(order.end(), lists[c].begin() + pos[c], lists[c].end());
+    return order;
+}
+
+int build_blocks(stdg_mesh* m, const std::vector<int64_t>& rep) {
+    const int N = m->N;
     m->blocks.assign((size_t)m->n_classes * 5 * N * N, 0.0);
     const NodalBasis phi(m->p);
     int bad = 0;
