@@ -124,6 +124,7 @@ class SpaceTimeOperators:
             FW = fw[:, None] * self.wtau[None, :] * dt
             n_ij = sigma * n_j                      # outward normal of T_i
             face_psph = np.einsum("mt,mtk,mtl->kl", FW, FPS, FPH)
+            out[("Qvol", s)] = Q.copy()             # volume part only
             for d in range(3):
                 Q[d] -= face_psph * sigma * n_j[d]
                 D[d] += face_psph.T * n_ij[d]
