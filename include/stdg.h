@@ -20,9 +20,11 @@
  *     perm[internal] = input element index.
  *   - Layouts (row-major, contiguous, device memory, 8-byte aligned):
  *       pressure      [E][G][N]      (time node, then spatial node)
- *       main velocity [E][3][G][N]
- *       dual velocity [F][3][G][N]   (faces in stdg_mesh_faces order, Taylor
- *                                     coefficients of eq. bf_2)
+ *       main velocity [3][E][G][N]   (component-major)
+ *       dual velocity [3][F][G][N]   (faces in stdg_mesh_faces order, Taylor
+ *                                     coefficients of eq. bf_2 about the volume
+ *                                     centroid of the dual element, scaled by
+ *                                     half its diameter)
  *     N = (p+1)(p+2)(p+3)/6 spatial nodes (j1,j2,j3)/p, j1 fastest then j2,
  *     then j3, on the element's own vertex order (local vertex 0 = reference
  *     origin); G = p_gamma+1 Gauss-Legendre time nodes of [0,1], ascending.
@@ -178,6 +180,66 @@ void stdg_solve_opts_default(stdg_solve_opts* opts);
 int stdg_pressure_solve(const stdg_mesh* mesh, const double* b, double* x,
                         const stdg_solve_opts* opts, stdg_solve_report* report,
                         void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Picard pressure-correction time step (Sec. 2.6, steps 0-6).
+ *
+ * Readings fixed where the paper is silent (its boundary terms are only in
+ * commented-out text): a Dirichlet face's dual element is the single
+ * sub-tetrahedron, its velocity is the projection of the nodal Dirichlet data
+ * of its element (the goback map with one side), it has no momentum equation
+ * and no pressure coupling; the viscous stress uses that data for the jump on
+ * the face; Lambda uses the element's own pressure gradient on a boundary
+ * sub-tetrahedron; the Rusanov ghost state is the boundary dual velocity.
+ */
+#define STDG_GUESS_ZERO 0       /* p^{n+1,0} = 0 (the paper's choice)        */
+#define STDG_GUESS_PREVIOUS 1   /* p^{n+1,0} = previous slab's pressure      */
+
+typedef struct {
+    int32_t n_picard;           /* Picard iterations; 0 = p_gamma + 1        */
+    int32_t pressure_guess;     /* STDG_GUESS_ZERO or STDG_GUESS_PREVIOUS    */
+    stdg_solve_opts pressure;   /* pressure-correction solves (eq. A2_mod)   */
+    stdg_solve_opts viscous;    /* viscous solves (eq. A1_mod), FP64 only    */
+} stdg_step_opts;
+
+typedef struct {
+    int32_t pressure_iters;     /* Krylov iterations, all Picard iterations  */
+    int32_t viscous_iters;
+    double max_pressure_residual;
+    double max_viscous_residual;
+    double seconds;
+} stdg_step_report;
+
+/* Defaults: n_picard 0, zero pressure guess, solve defaults, viscous rtol 1e-12. */
+void stdg_step_opts_default(stdg_step_opts* opts);
+
+/* Advance one slab.  vhat [3][F][G][N]: dual velocity of slab n on entry, of
+ * slab n+1 on exit; vbar [3][E][G][N]: averaged (eq. average) velocity of slab
+ * n on entry (used by Mbar^- of eq. A1_mod), of slab n+1 on exit; p [E][G][N]:
+ * pressure of slab n on entry (read only with STDG_GUESS_PREVIOUS), of slab
+ * n+1 on exit; g_nodal [3][E][G][N]: Dirichlet velocity at the element nodes
+ * of slab n+1 (only elements with boundary faces are read; NULL allowed on a
+ * mesh without boundary faces).  Device pointers; workspace is owned by the
+ * mesh handle.  Synchronises `stream`. */
+int stdg_picard_step(const stdg_mesh* mesh, double* vhat, double* vbar, double* p,
+                     const double* g_nodal, const stdg_step_opts* opts,
+                     stdg_step_report* report, void* stream);
+
+/* Dual velocity from a main-grid velocity by eq. goback (one-sided on
+ * boundary faces): the initial slab's vhat from nodal initial data.
+ * vbar [3][E][G][N] -> vhat [3][F][G][N].  Asynchronous. */
+int stdg_dual_from_main(const stdg_mesh* mesh, const double* vbar, double* vhat,
+                        void* stream);
+
+/* Main-grid velocity from the dual velocity by eq. average.
+ * vhat [3][F][G][N] -> vbar [3][E][G][N].  Asynchronous. */
+int stdg_main_from_dual(const stdg_mesh* mesh, const double* vhat, double* vbar,
+                        void* stream);
+
+/* Discrete divergence sum_{j in S_i} D_ij vhat_j (eq. CS_15), [E][G][N].
+ * Asynchronous. */
+int stdg_divergence(const stdg_mesh* mesh, const double* vhat, double* div,
+                    void* stream);
 
 /* Message of the last error on this thread ("" if none). */
 const char* stdg_last_error(void);

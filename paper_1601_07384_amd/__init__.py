@@ -11,12 +11,13 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (Config, MeshInfo, SolveOpts, SolveReport, StdgError,
+from ._lib import (Config, MeshInfo, SolveOpts, SolveReport, StepOpts, StepReport, StdgError,
                    STDG_OK, STDG_NOT_CONVERGED, STDG_FP64, STDG_FP32,
-                   STDG_AUTO, STDG_CG, STDG_GMRES)
+                   STDG_AUTO, STDG_CG, STDG_GMRES, STDG_GUESS_ZERO, STDG_GUESS_PREVIOUS)
 
 __all__ = ["Mesh", "StdgError", "STDG_FP64", "STDG_FP32", "STDG_AUTO",
-           "STDG_CG", "STDG_GMRES", "solve_opts"]
+           "STDG_CG", "STDG_GMRES", "STDG_GUESS_ZERO", "STDG_GUESS_PREVIOUS",
+           "solve_opts", "step_opts"]
 
 
 def _stream_ptr(stream):
@@ -37,6 +38,17 @@ def solve_opts(**kw):
         if not hasattr(o, k):
             raise TypeError(f"unknown solve option {k}")
         setattr(o, k, v)
+    return o
+
+
+def step_opts(n_picard=0, pressure_guess=0, pressure=None, viscous=None):
+    o = StepOpts()
+    _lib.load().stdg_step_opts_default(ctypes.byref(o))
+    o.n_picard = n_picard
+    o.pressure_guess = pressure_guess
+    for name, kw in (("pressure", pressure), ("viscous", viscous)):
+        for k, v in (kw or {}).items():
+            setattr(getattr(o, name), k, v)
     return o
 
 
@@ -122,6 +134,43 @@ class Mesh:
                                              ctypes.byref(rep), _stream_ptr(stream))
         _lib.check(code, allow=(STDG_OK, STDG_NOT_CONVERGED))
         return rep
+
+    # -------------------------------------------------------------- Picard
+    def picard_step(self, vhat, vbar, p, g_nodal=None, opts=None, stream=None, **kw):
+        """One time step (in place on vhat [3,F,G,N], vbar [3,E,G,N], p [E,G,N])."""
+        for t, n in ((vhat, 3 * self.n_face * self.Nst), (vbar, 3 * self.E * self.Nst),
+                     (p, self.E * self.Nst)):
+            self._check_any(t, n)
+        if g_nodal is not None:
+            self._check_any(g_nodal, 3 * self.E * self.Nst)
+        o = opts if opts is not None else step_opts(**kw)
+        rep = StepReport()
+        g = _ptr(g_nodal) if g_nodal is not None else None
+        _lib.check(self._lib.stdg_picard_step(self._h, _ptr(vhat), _ptr(vbar), _ptr(p), g,
+                                              ctypes.byref(o), ctypes.byref(rep),
+                                              _stream_ptr(stream)))
+        return rep
+
+    def dual_from_main(self, vbar, vhat, stream=None):
+        self._check_any(vbar, 3 * self.E * self.Nst)
+        self._check_any(vhat, 3 * self.n_face * self.Nst)
+        _lib.check(self._lib.stdg_dual_from_main(self._h, _ptr(vbar), _ptr(vhat), _stream_ptr(stream)))
+
+    def main_from_dual(self, vhat, vbar, stream=None):
+        self._check_any(vbar, 3 * self.E * self.Nst)
+        self._check_any(vhat, 3 * self.n_face * self.Nst)
+        _lib.check(self._lib.stdg_main_from_dual(self._h, _ptr(vhat), _ptr(vbar), _stream_ptr(stream)))
+
+    def divergence(self, vhat, div, stream=None):
+        self._check_any(vhat, 3 * self.n_face * self.Nst)
+        self._check_any(div, self.E * self.Nst)
+        _lib.check(self._lib.stdg_divergence(self._h, _ptr(vhat), _ptr(div), _stream_ptr(stream)))
+
+    def _check_any(self, t, n):
+        if not t.is_cuda or str(t.dtype) != "torch.float64" or not t.is_contiguous():
+            raise ValueError("expected a contiguous CUDA float64 tensor")
+        if t.numel() != n:
+            raise ValueError(f"expected {n} entries, got {t.numel()}")
 
     def _check_vec(self, t, dtype):
         if not t.is_cuda or str(t.dtype) != "torch." + dtype or not t.is_contiguous():

@@ -53,6 +53,21 @@ class SolveReport(ctypes.Structure):
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
+STDG_GUESS_ZERO = 0
+STDG_GUESS_PREVIOUS = 1
+
+
+class StepOpts(ctypes.Structure):
+    _fields_ = [("n_picard", ctypes.c_int32), ("pressure_guess", ctypes.c_int32),
+                ("pressure", SolveOpts), ("viscous", SolveOpts)]
+
+
+class StepReport(ctypes.Structure):
+    _fields_ = [("pressure_iters", ctypes.c_int32), ("viscous_iters", ctypes.c_int32),
+                ("max_pressure_residual", ctypes.c_double),
+                ("max_viscous_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
 # (name, restype, argtypes) of every symbol declared in include/stdg.h
 _P = ctypes.c_void_p
 SIGNATURES = [
@@ -70,6 +85,12 @@ SIGNATURES = [
     ("stdg_solve_opts_default", None, [ctypes.POINTER(SolveOpts)]),
     ("stdg_pressure_solve", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(SolveOpts),
                                             ctypes.POINTER(SolveReport), _P]),
+    ("stdg_step_opts_default", None, [ctypes.POINTER(StepOpts)]),
+    ("stdg_picard_step", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(StepOpts),
+                                         ctypes.POINTER(StepReport), _P]),
+    ("stdg_dual_from_main", ctypes.c_int, [_P, _P, _P, _P]),
+    ("stdg_main_from_dual", ctypes.c_int, [_P, _P, _P, _P]),
+    ("stdg_divergence", ctypes.c_int, [_P, _P, _P, _P]),
     ("stdg_last_error", ctypes.c_char_p, []),
 ]
 

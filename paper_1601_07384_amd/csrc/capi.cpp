@@ -92,12 +92,15 @@ static int mesh_build_impl(const double* xyz, int64_t n_vert, const int64_t* tet
             if (e == STDG_OK) e = assign_classes(m, rep);
         }
         if (e == STDG_OK) e = build_blocks(m, rep);
+        if (e == STDG_OK) e = build_picard_tables(m, rep);
         if (e == STDG_OK) {
             m->anchor = m->iperm[cfg->anchor_tet];
             m->anchor_node = cfg->anchor_node;
             if (device) e = upload_tables(m);
+            if (device && e == STDG_OK) e = upload_picard_tables(m);
         }
         if (e != STDG_OK) {
+            free_picard(m);
             free_tables(m);
             delete m;
             return e;
@@ -167,6 +170,7 @@ extern "C" int stdg_mesh_faces(const stdg_mesh* m, int64_t* left, int32_t* lf, i
 extern "C" void stdg_mesh_free(stdg_mesh* m) {
     if (!m) return;
     free_workspace(m);
+    free_picard(m);
     free_tables(m);
     delete m;
 }

@@ -54,6 +54,34 @@ struct Workspace {
     int64_t partial_len = 0;
 };
 
+V3 centroid(const std::array<V3, 4>& v);
+V3 neighbour_shift(const stdg_mesh* m, int64_t t, int f);   // brings the neighbour next to t
+void taylor_eval(const std::vector<std::array<int, 3>>& ex, const V3& x, const V3& x0, real h, real* out);
+
+// Spatial tables of the Picard step (Sec. 2.6), per element class c and
+// local face f, row-major N x N blocks (see picard_tables.cpp).
+struct PicardTables {
+    std::vector<double> A, GB, QT, US, UN, BB, SV, MI;
+    int qs = 0, qt = 0, qv = 0, nqf = 0, nqv = 0;
+    std::vector<double> cJinv, cdet, cnrm, PHf, PHn, FW, PHv, dPHv, wv, tq, tw, gq;
+    std::vector<double> Tm, TW, W, g0g1, g1;
+};
+
+struct PicardDevice {
+    double *A = nullptr, *GB = nullptr, *QT = nullptr, *US = nullptr, *UN = nullptr, *BB = nullptr;
+    double *SVT = nullptr, *MIT = nullptr;
+    double *cJinv = nullptr, *cdet = nullptr, *cnrm = nullptr, *PHf = nullptr, *PHn = nullptr, *FW = nullptr;
+    double *PHv = nullptr, *dPHv = nullptr, *wv = nullptr, *tq = nullptr, *tw = nullptr, *gq = nullptr;
+    double *Tm = nullptr, *TW = nullptr, *W = nullptr, *g0g1 = nullptr, *g1 = nullptr;
+    int64_t* tet_face = nullptr;     // [E][4]
+    int64_t* fl = nullptr;           // [F] left element
+    int64_t* fr = nullptr;           // [F] right element (-1 boundary)
+    int32_t* flf = nullptr;          // [F] left local face
+    int32_t* frf = nullptr;          // [F] right local face
+    double* work = nullptr;          // step workspace
+    size_t work_len = 0;
+};
+
 }  // namespace stdg
 
 struct stdg_mesh {
@@ -75,4 +103,6 @@ struct stdg_mesh {
     int anchor_node = 0;
     stdg::DeviceTables d;
     stdg::Workspace ws;
+    stdg::PicardTables pt;
+    stdg::PicardDevice pd;
 };

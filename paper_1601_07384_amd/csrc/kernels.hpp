@@ -6,12 +6,15 @@
 #include <cstdint>
 #include <vector>
 
+#include "../../include/stdg.h"
+
 struct stdg_mesh;
 
 namespace stdg {
 
 hipError_t launch_apply_f64(const stdg_mesh* m, const double* x, double* y, hipStream_t s);
 hipError_t launch_apply_f32(const stdg_mesh* m, const float* x, float* y, hipStream_t s);
+hipError_t launch_visc_apply(const stdg_mesh* m, const double* x, double* y, hipStream_t s);
 hipError_t convert_d2f(const double* a, float* b, int64_t n, hipStream_t s);
 hipError_t convert_f2d(const float* a, double* b, int64_t n, hipStream_t s);
 
@@ -22,5 +25,10 @@ std::vector<int64_t> class_chunk_order(const stdg_mesh* m);
 int build_blocks(stdg_mesh* m, const std::vector<int64_t>& rep);
 int upload_tables(stdg_mesh* m);
 void free_tables(stdg_mesh* m);
+int build_picard_tables(stdg_mesh* m, const std::vector<int64_t>& rep);
+int upload_picard_tables(stdg_mesh* m);
+void free_picard(stdg_mesh* m);
+int viscous_solve(stdg_mesh* m, const double* b, double* x, const stdg_solve_opts& o, double* work,
+                  hipStream_t s, int& iters, double& rel);
 
 }  // namespace stdg

@@ -321,14 +321,6 @@ int grid_for(int64_t n) {
     return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
 }
 
-template <typename T> struct Apply;
-template <> struct Apply<double> {
-    static hipError_t run(const stdg_mesh* m, const double* x, double* y, hipStream_t s) { return launch_apply_f64(m, x, y, s); }
-};
-template <> struct Apply<float> {
-    static hipError_t run(const stdg_mesh* m, const float* x, float* y, hipStream_t s) { return launch_apply_f32(m, x, y, s); }
-};
-
 struct Ctx {
     const stdg_mesh* m;
     hipStream_t s;
@@ -337,7 +329,20 @@ struct Ctx {
     double* scal;
     double* hscal;
     double* gm;        // GMRES small arrays: H, g, cs, sn, y, h
+    int op = 0;        // 0: pressure Schur operator, 1: viscous operator (3 components)
     int applies = 0;
+};
+
+template <typename T> struct Apply;
+template <> struct Apply<double> {
+    static hipError_t run(const Ctx& c, const double* x, double* y) {
+        return c.op == 0 ? launch_apply_f64(c.m, x, y, c.s) : launch_visc_apply(c.m, x, y, c.s);
+    }
+};
+template <> struct Apply<float> {
+    static hipError_t run(const Ctx& c, const float* x, float* y) {
+        return c.op == 0 ? launch_apply_f32(c.m, x, y, c.s) : hipErrorInvalidValue;
+    }
 };
 
 #define CK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { set_error(std::string(#x) + ": " + hipGetErrorString(e_)); return STDG_ERR_DEVICE; } } while (0)
@@ -366,7 +371,7 @@ int cg(Ctx& c, const T* b, T* x, T* r, T* p, T* q, double tol_abs, int max_it, i
        int& iters, double& res_out) {
     const int64_t n = c.n;
     const int gb = grid_for(n);
-    CK(Apply<T>::run(c.m, x, q, c.s)); c.applies++;
+    CK(Apply<T>::run(c, x, q)); c.applies++;
     hipLaunchKernelGGL((k_resid<T, T>), dim3(NBLK), dim3(RT), 0, c.s, b, q, r, n, c.partial);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_RR, (int)FIN_STORE);
     hipLaunchKernelGGL(k_copy<T>, dim3(gb), dim3(256), 0, c.s, r, p, n);
@@ -377,7 +382,7 @@ int cg(Ctx& c, const T* b, T* x, T* r, T* p, T* q, double tol_abs, int max_it, i
     res_out = std::sqrt(rr);
     if (res_out <= tol_abs) return STDG_OK;
     while (iters < max_it) {
-        CK(Apply<T>::run(c.m, p, q, c.s)); c.applies++;
+        CK(Apply<T>::run(c, p, q)); c.applies++;
         hipLaunchKernelGGL((k_dot<T, T>), dim3(NBLK), dim3(RT), 0, c.s, p, q, n, c.partial);
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, 0, (int)FIN_CG_ALPHA);
         hipLaunchKernelGGL(k_cg_xr<T>, dim3(NBLK), dim3(RT), 0, c.s, x, r, p, q, c.scal, n, c.partial);
@@ -410,7 +415,7 @@ int gmres(Ctx& c, const T* b, T* x, T* r, T* V, int mres, double tol_abs, int ma
     iters = 0;
     while (true) {
         // r = b - S x, beta = ||r||, V_0 = r / beta
-        CK(Apply<T>::run(c.m, x, r, c.s)); c.applies++;
+        CK(Apply<T>::run(c, x, r)); c.applies++;
         hipLaunchKernelGGL((k_resid<T, T>), dim3(NBLK), dim3(RT), 0, c.s, b, r, V, n, c.partial);
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_NORM, (int)FIN_SQRT);
         double beta;
@@ -427,7 +432,7 @@ int gmres(Ctx& c, const T* b, T* x, T* r, T* V, int mres, double tol_abs, int ma
         bool conv = false;
         for (; k < mres && iters < max_it; ++k) {
             T* w = V + (int64_t)(k + 1) * n;
-            CK(Apply<T>::run(c.m, V + (int64_t)k * n, w, c.s)); c.applies++;
+            CK(Apply<T>::run(c, V + (int64_t)k * n, w)); c.applies++;
             double* Hk = H + (int64_t)(mres + 1) * k;
             for (int pass = 0; pass < 2; ++pass) {
                 hipLaunchKernelGGL(k_multidot<T>, dim3(NBLK), dim3(RT), 0, c.s, V, k + 1, n, w, c.partial);
@@ -501,6 +506,63 @@ void free_workspace(stdg_mesh* m) {
         if (p) (void)hipFree(p);
     if (w.hscal) (void)hipHostFree(w.hscal);
     w = Workspace();
+}
+
+// Plain (non-singular) solve A_v x = b of the viscous system with the
+// library's CG/GMRES; x holds the guess.  Vectors [3][E][G][N]; work vectors
+// are taken from `work` (needs (restart + 4) * n doubles for GMRES, 4 n for CG).
+int viscous_solve(stdg_mesh* m, const double* b, double* x, const stdg_solve_opts& o, double* work,
+                  hipStream_t s, int& iters, double& rel) {
+    if (int e = ensure_workspace(m, 0, false)) return e;
+    Ctx c;
+    c.m = m;
+    c.s = s;
+    c.n = 3 * m->E * m->Nst;
+    c.partial = m->ws.partial;
+    c.scal = m->ws.scal;
+    c.hscal = m->ws.hscal;
+    c.gm = m->ws.scal + S_COUNT;
+    c.op = 1;
+    const int64_t n = c.n;
+    double* r = work;
+    double* pp = work + n;
+    double* q = work + 2 * n;
+    double* V = work + 3 * n;
+    const int method = o.method == STDG_AUTO ? (m->G == 1 ? STDG_CG : STDG_GMRES) : o.method;
+    hipLaunchKernelGGL((k_dot<double, double>), dim3(NBLK), dim3(RT), 0, s, b, b, n, c.partial);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, c.partial, NBLK, c.scal, (int)S_BN2, (int)FIN_STORE);
+    double bn2;
+    if (int e = read_scal(c, S_BN2, bn2)) return e;
+    if (!std::isfinite(bn2)) { set_error("non-finite viscous right-hand side"); return STDG_ERR_NUMERIC; }
+    const double bn = std::sqrt(bn2);
+    iters = 0;
+    rel = 0.0;
+    if (bn == 0.0) {
+        hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(256), 0, s, x, 0.0, n);
+        return STDG_OK;
+    }
+    double tol = o.rtol * bn;
+    int status = STDG_OK;
+    for (int round = 0; round < 6; ++round) {
+        int it = 0;
+        double res = 0.0;
+        const int left = o.max_iter - iters;
+        if (left <= 0) { status = STDG_NOT_CONVERGED; break; }
+        status = run_krylov<double>(c, method, b, x, r, pp, q, V, o.restart, tol, left, o.check_every, it, res);
+        iters += it;
+        if (status < 0) return status;
+        // true residual
+        CK(launch_visc_apply(m, x, q, s));
+        hipLaunchKernelGGL((k_resid<double, double>), dim3(NBLK), dim3(RT), 0, s, b, q, r, n, c.partial);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, c.partial, NBLK, c.scal, (int)S_RN2, (int)FIN_STORE);
+        double rn2;
+        if (int e = read_scal(c, S_RN2, rn2)) return e;
+        rel = std::sqrt(rn2) / bn;
+        if (rel <= o.rtol) { status = STDG_OK; break; }
+        if (status == STDG_NOT_CONVERGED) break;
+        tol *= 0.25;
+    }
+    return status;
 }
 
 }  // namespace stdg

@@ -57,6 +57,8 @@ struct TriHash {
     }
 };
 
+}  // namespace
+
 V3 centroid(const std::array<V3, 4>& v) {
     return {(v[0][0] + v[1][0] + v[2][0] + v[3][0]) / 4, (v[0][1] + v[1][1] + v[2][1] + v[3][1]) / 4,
             (v[0][2] + v[1][2] + v[2][2] + v[3][2]) / 4};
@@ -75,8 +77,6 @@ void taylor_eval(const std::vector<std::array<int, 3>>& ex, const V3& x, const V
     }
     for (size_t r = 0; r < ex.size(); ++r) out[r] = pw[0][ex[r][0]] * pw[1][ex[r][1]] * pw[2][ex[r][2]];
 }
-
-}  // namespace
 
 // Dual-element data of one face seen from element t (side 0) and its
 // neighbour (side 1): the spatial Q blocks (3 x N x N, rows = dual basis) of
@@ -161,7 +161,6 @@ static void dual_face_blocks(const NodalBasis& phi, int p, const std::array<V3, 
     }
 }
 
-static V3 neighbour_shift(const stdg_mesh* m, int64_t t, int f);
 
 // Five dt^2-scaled spatial blocks of element t: [0] diagonal, [1+f] coupling
 // to the neighbour across local face f (zero on a boundary face).
@@ -358,7 +357,7 @@ int build_topology(stdg_mesh* m, const double* xyz, int64_t n_vert, const int64_
 }
 
 // Translation that brings the neighbour across local face f next to t.
-static V3 neighbour_shift(const stdg_mesh* m, int64_t t, int f) {
+V3 neighbour_shift(const stdg_mesh* m, int64_t t, int f) {
     const Face& F = m->faces[m->tet_face[t * 4 + f]];
     if (F.left == t && F.lf == f) return F.shift;          // neighbour is the right element
     return scale(F.shift, -1.0);                           // neighbour is the left element

@@ -1,0 +1,592 @@
+// One Picard pressure-correction time step of the staggered space-time DG
+// scheme (Sec. 2.6, steps 0-6) on the device, with the tables built by
+// picard_tables.cpp.
+//
+// Layouts: dual velocity [3][F][G][N] (faces in the library's order: interior
+// first, then boundary), main-grid velocity [3][E][G][N], pressure [E][G][N].
+// Every spatial block is N x N row-major; a kernel thread computes one output
+// row r of one (component, element or face, time node).
+#include <chrono>
+#include <cmath>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace stdg {
+
+namespace {
+
+#define CKP(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { set_error(std::string(#x) + ": " + hipGetErrorString(e_)); return STDG_ERR_DEVICE; } } while (0)
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// value at the end of the previous slab, broadcast over the new slab's nodes
+__global__ void k_time_end(const double* __restrict__ in, double* __restrict__ out,
+                           const double* __restrict__ g1, int64_t rows, int G, int N) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (row, n)
+    if (t >= rows * N) return;
+    const int64_t row = t / N;
+    const int n = (int)(t - row * N);
+    double s = 0.0;
+    for (int b = 0; b < G; ++b) s += g1[b] * in[(row * G + b) * N + n];
+    for (int a = 0; a < G; ++a) out[(row * G + a) * N + n] = s;
+}
+
+// eq. goback: Fv_j = GB_l vbar_l + GB_r vbar_r (interior); one side from
+// `vbdry` on boundary faces (the projected Dirichlet data).  Faces [f0, f1).
+__global__ void k_goback(const double* __restrict__ GB, const int32_t* __restrict__ cls,
+                         const int64_t* __restrict__ fl, const int32_t* __restrict__ flf,
+                         const int64_t* __restrict__ fr, const int32_t* __restrict__ frf,
+                         const double* __restrict__ vbar, const double* __restrict__ vbdry,
+                         double* __restrict__ out, int64_t f0, int64_t f1, int64_t F, int64_t E,
+                         int G, int N) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nf = f1 - f0;
+    if (t >= 3 * nf * G * N) return;
+    const int r = (int)(t % N);
+    const int a = (int)((t / N) % G);
+    const int64_t j = f0 + (t / ((int64_t)N * G)) % nf;
+    const int c = (int)(t / ((int64_t)N * G * nf));
+    const int64_t l = fl[j], rr = fr[j];
+    const double* src = rr >= 0 ? vbar : vbdry;
+    const double* B = GB + (((int64_t)cls[l] * 4 + flf[j]) * N + r) * N;
+    const double* x = src + ((c * E + l) * G + a) * N;
+    double s = 0.0;
+    for (int m = 0; m < N; ++m) s += B[m] * x[m];
+    if (rr >= 0) {
+        const double* B2 = GB + (((int64_t)cls[rr] * 4 + frf[j]) * N + r) * N;
+        const double* x2 = vbar + ((c * E + rr) * G + a) * N;
+        for (int m = 0; m < N; ++m) s += B2[m] * x2[m];
+    }
+    out[((c * F + j) * G + a) * N + r] = s;
+}
+
+// eq. average: vbar_i = sum_f A_f vhat_face(i,f)   (3 components)
+__global__ void k_average(const double* __restrict__ A, const int32_t* __restrict__ cls,
+                          const int64_t* __restrict__ tet_face, const double* __restrict__ vhat,
+                          double* __restrict__ vbar, int64_t E, int64_t F, int G, int N) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * E * G * N) return;
+    const int r = (int)(t % N);
+    const int a = (int)((t / N) % G);
+    const int64_t i = (t / ((int64_t)N * G)) % E;
+    const int c = (int)(t / ((int64_t)N * G * E));
+    double s = 0.0;
+    for (int f = 0; f < 4; ++f) {
+        const int64_t j = tet_face[4 * i + f];
+        const double* B = A + (((int64_t)cls[i] * 4 + f) * N + r) * N;
+        const double* x = vhat + ((c * F + j) * G + a) * N;
+        for (int m = 0; m < N; ++m) s += B[m] * x[m];
+    }
+    vbar[((c * E + i) * G + a) * N + r] = s;
+}
+
+// Dual-grid pressure gradient (eqs. prevpress / A3_mod):
+// w_j[d][a] = dt sum_b TW_ab (US_d p_l[b] + UN_d p_r[b]) with the left
+// element's tables; boundary faces: US (volume part) only.
+__global__ void k_dualgrad(const double* __restrict__ US, const double* __restrict__ UN,
+                           const int32_t* __restrict__ cls, const int64_t* __restrict__ fl,
+                           const int32_t* __restrict__ flf, const int64_t* __restrict__ fr,
+                           const double* __restrict__ TW, const double* __restrict__ p, double dt,
+                           double* __restrict__ w, int64_t F, int G, int N) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * F * G * N) return;
+    const int r = (int)(t % N);
+    const int a = (int)((t / N) % G);
+    const int64_t j = (t / ((int64_t)N * G)) % F;
+    const int d = (int)(t / ((int64_t)N * G * F));
+    const int64_t l = fl[j], rr = fr[j];
+    const int64_t blk = (((int64_t)cls[l] * 4 + flf[j]) * 3 + d) * N + r;
+    const double* Bs = US + blk * N;
+    const double* Bn = UN + blk * N;
+    double s = 0.0;
+    for (int b = 0; b < G; ++b) {
+        const double tw = TW[a * G + b];
+        if (tw == 0.0) continue;
+        const double* pl = p + (l * G + b) * N;
+        double u = 0.0;
+        for (int m = 0; m < N; ++m) u += Bs[m] * pl[m];
+        if (rr >= 0) {
+            const double* pr = p + (rr * G + b) * N;
+            for (int m = 0; m < N; ++m) u += Bn[m] * pr[m];
+        }
+        s += tw * u;
+    }
+    w[((d * F + j) * G + a) * N + r] = dt * s;
+}
+
+// Viscous right-hand side (eq. A1_mod):
+// Mbar_i^- vbar^n - Upsilon - Mbar_i Lambda - nu dt sum_bdry (BB (x) W) vbc
+__global__ void k_visc_rhs(const double* __restrict__ MI, const double* __restrict__ BB,
+                           const int32_t* __restrict__ cls, const int32_t* __restrict__ nbr,
+                           const int64_t* __restrict__ tet_face, const double* __restrict__ g0g1,
+                           const double* __restrict__ Tm, const double* __restrict__ W,
+                           const double* __restrict__ vprev, const double* __restrict__ ups,
+                           const double* __restrict__ lam, const double* __restrict__ vbc,
+                           double nu_dt, double* __restrict__ rhs, int64_t E, int64_t F, int G, int N) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * E * G * N) return;
+    const int r = (int)(t % N);
+    const int a = (int)((t / N) % G);
+    const int64_t i = (t / ((int64_t)N * G)) % E;
+    const int c = (int)(t / ((int64_t)N * G * E));
+    const double* Mr = MI + ((int64_t)cls[i] * N + r) * N;
+    double s = 0.0;
+    for (int b = 0; b < G; ++b) {
+        const double* xp = vprev + ((c * E + i) * G + b) * N;
+        const double* xl = lam + ((c * E + i) * G + b) * N;
+        double u1 = 0.0, u2 = 0.0;
+        for (int m = 0; m < N; ++m) {
+            u1 += Mr[m] * xp[m];
+            u2 += Mr[m] * xl[m];
+        }
+        s += g0g1[a * G + b] * u1 - Tm[a * G + b] * u2;
+    }
+    s -= ups[((c * E + i) * G + a) * N + r];
+    for (int f = 0; f < 4; ++f) {
+        if (nbr[4 * i + f] >= 0) continue;
+        const int64_t j = tet_face[4 * i + f];
+        const double* Br = BB + (((int64_t)cls[i] * 4 + f) * N + r) * N;
+        const double* xb = vbc + ((c * F + j) * G + a) * N;
+        double u = 0.0;
+        for (int m = 0; m < N; ++m) u += Br[m] * xb[m];
+        s -= nu_dt * W[a] * u;
+    }
+    rhs[((c * E + i) * G + a) * N + r] = s;
+}
+
+// pressure right-hand side (eq. A2_mod): b_i = dt W_a sum_f sum_d QT_fd Fv_face[d][a]
+__global__ void k_rhs_pressure(const double* __restrict__ QT, const int32_t* __restrict__ cls,
+                               const int64_t* __restrict__ tet_face, const double* __restrict__ W,
+                               const double* __restrict__ Fv, double dt, double* __restrict__ b,
+                               int64_t E, int64_t F, int G, int N) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= E * G * N) return;
+    const int r = (int)(t % N);
+    const int a = (int)((t / N) % G);
+    const int64_t i = t / ((int64_t)N * G);
+    double s = 0.0;
+    for (int f = 0; f < 4; ++f) {
+        const int64_t j = tet_face[4 * i + f];
+        for (int d = 0; d < 3; ++d) {
+            const double* B = QT + ((((int64_t)cls[i] * 4 + f) * 3 + d) * N + r) * N;
+            const double* x = Fv + ((d * F + j) * G + a) * N;
+            for (int m = 0; m < N; ++m) s += B[m] * x[m];
+        }
+    }
+    b[(i * G + a) * N + r] = dt * W[a] * s;
+}
+
+// eq. A3_mod: vhat = Fv - w on interior faces, the prescribed data on boundary faces
+__global__ void k_update(const double* __restrict__ Fv, const double* __restrict__ w,
+                         double* __restrict__ vhat, int64_t F, int64_t n_int, int G, int N) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * F * G * N) return;
+    const int64_t j = (t / ((int64_t)N * G)) % F;
+    vhat[t] = j < n_int ? Fv[t] - w[t] : Fv[t];
+}
+
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] += a * x[t];
+}
+
+__global__ void k_copyd(const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = x[t];
+}
+
+__global__ void k_zero(double* __restrict__ y, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = 0.0;
+}
+
+// Viscous operator (eq. A1_mod): y = (MI (x) T) x_i + nu dt sum_k (SV_k (x) W) x_nb(k)
+__global__ void k_visc_apply(const double* __restrict__ SV, const double* __restrict__ MI,
+                             const int32_t* __restrict__ cls, const int32_t* __restrict__ nbr,
+                             const double* __restrict__ Tm, const double* __restrict__ W, double nu_dt,
+                             const double* __restrict__ x, double* __restrict__ y, int64_t E, int G, int N) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * E * G * N) return;
+    const int r = (int)(t % N);
+    const int a = (int)((t / N) % G);
+    const int64_t i = (t / ((int64_t)N * G)) % E;
+    const int c = (int)(t / ((int64_t)N * G * E));
+    const int64_t cbase = (int64_t)c * E;
+    double s = 0.0;
+    for (int k = 0; k < 5; ++k) {
+        const int64_t nb = k == 0 ? i : (int64_t)nbr[4 * i + k - 1];
+        if (nb < 0) continue;
+        const double* B = SV + (((int64_t)cls[i] * 5 + k) * N + r) * N;
+        const double* xk = x + ((cbase + nb) * G + a) * N;
+        double u = 0.0;
+        for (int m = 0; m < N; ++m) u += B[m] * xk[m];
+        s += nu_dt * W[a] * u;
+    }
+    const double* Mr = MI + ((int64_t)cls[i] * N + r) * N;
+    for (int b = 0; b < G; ++b) {
+        const double* xb = x + ((cbase + i) * G + b) * N;
+        double u = 0.0;
+        for (int m = 0; m < N; ++m) u += Mr[m] * xb[m];
+        s += Tm[a * G + b] * u;
+    }
+    y[t] = s;
+}
+
+// Space-time DG convection with the Rusanov flux (eq. convdg), one block of
+// 64 threads per element.  For each time point of the rule: the lanes first
+// evaluate the velocity at the volume points (flux tensor pulled back by the
+// element Jacobian) and at the four faces' points (Rusanov flux, own trace
+// against the neighbour's trace or the boundary dual velocity) into LDS; then
+// each lane accumulates the test-function sums for its outputs (c, k).
+template <int N, int G>
+__global__ void __launch_bounds__(64) k_convection(
+    const double* __restrict__ vbar, const double* __restrict__ vbc, const int32_t* __restrict__ cls,
+    const int32_t* __restrict__ nbr, const int64_t* __restrict__ tet_face, const double* __restrict__ cJinv,
+    const double* __restrict__ cdet, const double* __restrict__ cnrm, const double* __restrict__ PHf,
+    const double* __restrict__ PHn, const double* __restrict__ FW, const double* __restrict__ PHv,
+    const double* __restrict__ dPHv, const double* __restrict__ wv, const double* __restrict__ tw,
+    const double* __restrict__ gq, int nqv, int nqf, int qt, double dt, double* __restrict__ ups,
+    int64_t E, int64_t F) {
+    extern __shared__ double sh[];
+    double* vol = sh;                      // [nqv][3][3]  w |J| (J^-T) (v v^T)
+    double* fac = sh + (size_t)nqv * 9;    // [4][nqf][3]  w area * flux
+    const int64_t i = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int c = cls[i];
+    const double* Ji = cJinv + (int64_t)c * 9;
+    const double det = cdet[c];
+    constexpr int NOUT = 3 * N;
+    constexpr int NP = (NOUT + 63) / 64;   // outputs per lane
+    double acc[NP][G];
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int a = 0; a < G; ++a) acc[u][a] = 0.0;
+    for (int t = 0; t < qt; ++t) {
+        double gt[G];
+#pragma unroll
+        for (int b = 0; b < G; ++b) gt[b] = gq[t * G + b];
+        const double wt = tw[t];
+        // ---- phase A: volume points
+        for (int q = lane; q < nqv; q += 64) {
+            double v[3] = {0, 0, 0};
+            const double* ph = PHv + (int64_t)q * N;
+            for (int cc = 0; cc < 3; ++cc)
+                for (int b = 0; b < G; ++b) {
+                    const double* x = vbar + ((cc * E + i) * G + b) * N;
+                    double s = 0.0;
+                    for (int n = 0; n < N; ++n) s += ph[n] * x[n];
+                    v[cc] += gt[b] * s;
+                }
+            const double w = wt * wv[q] * det;
+            for (int cc = 0; cc < 3; ++cc)
+                for (int e = 0; e < 3; ++e) {
+                    // sum_d Jinv[e][d] F_cd, F_cd = v_c v_d
+                    double s = Ji[e * 3 + 0] * v[0] + Ji[e * 3 + 1] * v[1] + Ji[e * 3 + 2] * v[2];
+                    vol[(q * 3 + cc) * 3 + e] = w * v[cc] * s;
+                }
+        }
+        // ---- phase A: face points
+        for (int qq = lane; qq < 4 * nqf; qq += 64) {
+            const int f = qq / nqf, q = qq - f * nqf;
+            const int64_t off = ((int64_t)c * 4 + f) * nqf + q;
+            const double* ph = PHf + off * N;
+            const double* pn = PHn + off * N;
+            const int64_t k = nbr[4 * i + f];
+            double vm[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
+            for (int cc = 0; cc < 3; ++cc)
+                for (int b = 0; b < G; ++b) {
+                    const double* xm = vbar + ((cc * E + i) * G + b) * N;
+                    const double* xp = k >= 0 ? vbar + ((cc * E + k) * G + b) * N
+                                              : vbc + ((cc * F + tet_face[4 * i + f]) * G + b) * N;
+                    double sm = 0.0, sp = 0.0;
+                    for (int n = 0; n < N; ++n) {
+                        sm += ph[n] * xm[n];
+                        sp += pn[n] * xp[n];
+                    }
+                    vm[cc] += gt[b] * sm;
+                    vp[cc] += gt[b] * sp;
+                }
+            const double* nr = cnrm + (int64_t)c * 12 + f * 3;
+            const double unm = vm[0] * nr[0] + vm[1] * nr[1] + vm[2] * nr[2];
+            const double unp = vp[0] * nr[0] + vp[1] * nr[1] + vp[2] * nr[2];
+            const double am = sqrt(vm[0] * vm[0] + vm[1] * vm[1] + vm[2] * vm[2]);
+            const double ap = sqrt(vp[0] * vp[0] + vp[1] * vp[1] + vp[2] * vp[2]);
+            const double smax = 2.0 * (am > ap ? am : ap);
+            const double w = wt * FW[off];
+            for (int cc = 0; cc < 3; ++cc)
+                fac[qq * 3 + cc] = w * (0.5 * (vp[cc] * unp + vm[cc] * unm) - 0.5 * smax * (vp[cc] - vm[cc]));
+        }
+        __syncthreads();
+        // ---- phase B: test-function sums for outputs (cc, kk)
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+            const int o = lane + 64 * u;
+            if (o >= NOUT) continue;
+            const int cc = o / N, kk = o - cc * N;
+            double s = 0.0;
+            for (int q = 0; q < nqv; ++q) {
+                const double* dp = dPHv + ((int64_t)q * N + kk) * 3;
+                const double* vq = vol + (q * 3 + cc) * 3;
+                s -= dp[0] * vq[0] + dp[1] * vq[1] + dp[2] * vq[2];
+            }
+            for (int f = 0; f < 4; ++f)
+                for (int q = 0; q < nqf; ++q) {
+                    const int64_t off = ((int64_t)c * 4 + f) * nqf + q;
+                    s += PHf[off * N + kk] * fac[(f * nqf + q) * 3 + cc];
+                }
+#pragma unroll
+            for (int a = 0; a < G; ++a) acc[u][a] += gt[a] * s;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+        const int o = lane + 64 * u;
+        if (o >= NOUT) continue;
+        const int cc = o / N, kk = o - cc * N;
+#pragma unroll
+        for (int a = 0; a < G; ++a) ups[((cc * E + i) * G + a) * N + kk] = dt * acc[u][a];
+    }
+}
+
+template <int N, int G>
+hipError_t launch_conv_ng(const stdg_mesh* m, const double* vbar, const double* vbc, double* ups, hipStream_t s) {
+    const PicardTables& t = m->pt;
+    const PicardDevice& d = m->pd;
+    const size_t lds = ((size_t)t.nqv * 9 + (size_t)4 * t.nqf * 3) * sizeof(double);
+    hipLaunchKernelGGL((k_convection<N, G>), dim3((unsigned)m->E), dim3(64), lds, s, vbar, vbc, m->d.cls,
+                       m->d.nbr, d.tet_face, d.cJinv, d.cdet, d.cnrm, d.PHf, d.PHn, d.FW, d.PHv, d.dPHv, d.wv,
+                       d.tw, d.gq, t.nqv, t.nqf, t.qt, m->cfg.dt, ups, m->E, (int64_t)m->faces.size());
+    return hipGetLastError();
+}
+
+hipError_t launch_convection(const stdg_mesh* m, const double* vbar, const double* vbc, double* ups,
+                             hipStream_t s) {
+#define STDG_CV(n, g) \
+    if (m->N == n && m->G == g) return launch_conv_ng<n, g>(m, vbar, vbc, ups, s);
+    STDG_CV(4, 1) STDG_CV(4, 2) STDG_CV(4, 3) STDG_CV(4, 4) STDG_CV(4, 5)
+    STDG_CV(10, 1) STDG_CV(10, 2) STDG_CV(10, 3) STDG_CV(10, 4) STDG_CV(10, 5)
+    STDG_CV(20, 1) STDG_CV(20, 2) STDG_CV(20, 3) STDG_CV(20, 4) STDG_CV(20, 5)
+    STDG_CV(35, 1) STDG_CV(35, 2) STDG_CV(35, 3) STDG_CV(35, 4) STDG_CV(35, 5)
+#undef STDG_CV
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+int upload(T*& dst, const std::vector<T>& src) {
+    if (src.empty()) { dst = nullptr; return STDG_OK; }
+    STDG_HIP(hipMalloc(&dst, src.size() * sizeof(T)));
+    STDG_HIP(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return STDG_OK;
+}
+
+}  // namespace
+
+hipError_t launch_visc_apply(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
+    const PicardDevice& d = m->pd;
+    const int64_t n = 3 * m->E * m->Nst;
+    hipLaunchKernelGGL(k_visc_apply, dim3(nblk(n)), dim3(256), 0, s, d.SVT, d.MIT, m->d.cls, m->d.nbr, d.Tm, d.W,
+                       m->cfg.nu * m->cfg.dt, x, y, m->E, m->G, m->N);
+    return hipGetLastError();
+}
+
+int upload_picard_tables(stdg_mesh* m) {
+    PicardTables& t = m->pt;
+    PicardDevice& d = m->pd;
+    int e = STDG_OK;
+    for (auto pr : std::initializer_list<std::pair<double**, std::vector<double>*>>{
+             {&d.A, &t.A}, {&d.GB, &t.GB}, {&d.QT, &t.QT}, {&d.US, &t.US}, {&d.UN, &t.UN}, {&d.BB, &t.BB},
+             {&d.SVT, &t.SV}, {&d.MIT, &t.MI}, {&d.cJinv, &t.cJinv}, {&d.cdet, &t.cdet}, {&d.cnrm, &t.cnrm},
+             {&d.PHf, &t.PHf}, {&d.PHn, &t.PHn}, {&d.FW, &t.FW}, {&d.PHv, &t.PHv}, {&d.dPHv, &t.dPHv},
+             {&d.wv, &t.wv}, {&d.tq, &t.tq}, {&d.tw, &t.tw}, {&d.gq, &t.gq}, {&d.Tm, &t.Tm}, {&d.TW, &t.TW},
+             {&d.W, &t.W}, {&d.g0g1, &t.g0g1}, {&d.g1, &t.g1}})
+        if ((e = upload(*pr.first, *pr.second))) return e;
+    const int64_t F = (int64_t)m->faces.size();
+    std::vector<int64_t> fl(F), fr(F);
+    std::vector<int32_t> flf(F), frf(F);
+    for (int64_t j = 0; j < F; ++j) {
+        fl[j] = m->faces[j].left; fr[j] = m->faces[j].right;
+        flf[j] = m->faces[j].lf; frf[j] = m->faces[j].rf;
+    }
+    if ((e = upload(d.fl, fl)) || (e = upload(d.fr, fr)) || (e = upload(d.flf, flf)) || (e = upload(d.frf, frf)) ||
+        (e = upload(d.tet_face, m->tet_face)))
+        return e;
+    return STDG_OK;
+}
+
+void free_picard(stdg_mesh* m) {
+    PicardDevice& d = m->pd;
+    for (void* p : {(void*)d.A, (void*)d.GB, (void*)d.QT, (void*)d.US, (void*)d.UN, (void*)d.BB, (void*)d.SVT,
+                    (void*)d.MIT, (void*)d.cJinv, (void*)d.cdet, (void*)d.cnrm, (void*)d.PHf, (void*)d.PHn,
+                    (void*)d.FW, (void*)d.PHv, (void*)d.dPHv, (void*)d.wv, (void*)d.tq, (void*)d.tw, (void*)d.gq,
+                    (void*)d.Tm, (void*)d.TW, (void*)d.W, (void*)d.g0g1, (void*)d.g1, (void*)d.tet_face,
+                    (void*)d.fl, (void*)d.fr, (void*)d.flf, (void*)d.frf, (void*)d.work})
+        if (p) (void)hipFree(p);
+    d = PicardDevice();
+}
+
+}  // namespace stdg
+
+using namespace stdg;
+
+extern "C" void stdg_step_opts_default(stdg_step_opts* o) {
+    if (!o) return;
+    o->n_picard = 0;
+    o->pressure_guess = STDG_GUESS_ZERO;
+    stdg_solve_opts_default(&o->pressure);
+    stdg_solve_opts_default(&o->viscous);
+    o->viscous.rtol = 1e-12;
+}
+
+extern "C" int stdg_dual_from_main(const stdg_mesh* m, const double* vbar, double* vhat, void* stream) {
+    if (!m || !vbar || !vhat) { set_error("null argument"); return STDG_ERR_ARG; }
+    if (!m->d.blocks || !m->pd.GB) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
+    const int64_t F = (int64_t)m->faces.size();
+    const int64_t n = 3 * F * m->Nst;
+    hipLaunchKernelGGL(k_goback, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, m->pd.GB, m->d.cls, m->pd.fl,
+                       m->pd.flf, m->pd.fr, m->pd.frf, vbar, vbar, vhat, (int64_t)0, F, F, m->E, m->G, m->N);
+    STDG_HIP(hipGetLastError());
+    return STDG_OK;
+}
+
+extern "C" int stdg_main_from_dual(const stdg_mesh* m, const double* vhat, double* vbar, void* stream) {
+    if (!m || !vbar || !vhat) { set_error("null argument"); return STDG_ERR_ARG; }
+    if (!m->d.blocks || !m->pd.A) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
+    const int64_t n = 3 * m->E * m->Nst;
+    hipLaunchKernelGGL(k_average, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, m->pd.A, m->d.cls,
+                       m->pd.tet_face, vhat, vbar, m->E, (int64_t)m->faces.size(), m->G, m->N);
+    STDG_HIP(hipGetLastError());
+    return STDG_OK;
+}
+
+extern "C" int stdg_divergence(const stdg_mesh* m, const double* vhat, double* div, void* stream) {
+    if (!m || !vhat || !div) { set_error("null argument"); return STDG_ERR_ARG; }
+    if (!m->d.blocks || !m->pd.QT) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
+    // sum_j D_ij vhat_j = -sum_j Q_ij^T vhat_j
+    const int64_t n = m->E * m->Nst;
+    hipLaunchKernelGGL(k_rhs_pressure, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, m->pd.QT, m->d.cls,
+                       m->pd.tet_face, m->pd.W, vhat, -m->cfg.dt, div, m->E, (int64_t)m->faces.size(), m->G, m->N);
+    STDG_HIP(hipGetLastError());
+    return STDG_OK;
+}
+
+extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar, double* p, const double* g_nodal,
+                                const stdg_step_opts* opts, stdg_step_report* rep, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!cm || !vhat || !vbar || !p || !opts) { set_error("null argument"); return STDG_ERR_ARG; }
+    stdg_mesh* m = const_cast<stdg_mesh*>(cm);
+    if (!m->d.blocks || !m->pd.A) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
+    const int64_t F = (int64_t)m->faces.size(), E = m->E, NI = m->n_interior;
+    if (F > NI && !g_nodal) { set_error("Dirichlet data required on a mesh with boundary faces"); return STDG_ERR_ARG; }
+    const int npic = opts->n_picard > 0 ? opts->n_picard : m->G;
+    if (opts->pressure_guess != STDG_GUESS_ZERO && opts->pressure_guess != STDG_GUESS_PREVIOUS) {
+        set_error("unknown pressure guess");
+        return STDG_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int G = m->G, N = m->N;
+    const int64_t nD = 3 * F * G * N, nM = 3 * E * G * N, nP = E * G * N;
+    const int mres = std::max(1, opts->viscous.restart);
+    // workspace: 4 dual + 6 main + 3 pressure vectors + viscous Krylov (mres + 4) main
+    const size_t need = 4 * nD + 6 * nM + 3 * nP + (size_t)(mres + 4) * nM;
+    PicardDevice& d = m->pd;
+    if (d.work_len < need) {
+        if (d.work) STDG_HIP(hipFree(d.work));
+        d.work = nullptr;
+        STDG_HIP(hipMalloc(&d.work, need * sizeof(double)));
+        d.work_len = need;
+    }
+    double* vk = d.work;            // dual velocity of the current iterate
+    double* Fv = vk + nD;
+    double* wg = Fv + nD;           // dual-grid pressure gradient
+    double* vbc = wg + nD;          // prescribed boundary dual velocity
+    double* vbk = vbc + nD;         // averaged velocity
+    double* lam = vbk + nM;
+    double* ups = lam + nM;
+    double* rhs = ups + nM;
+    double* vhalf = rhs + nM;
+    double* vprev = vhalf + nM;
+    double* pk = vprev + nM;
+    double* bp = pk + nP;
+    double* dp = bp + nP;
+    double* kw = dp + nP;           // viscous Krylov work
+    const double dt = m->cfg.dt;
+    // step 0
+    hipLaunchKernelGGL(k_copyd, dim3(nblk(nM)), dim3(256), 0, s, vbar, vprev, nM);
+    hipLaunchKernelGGL(k_time_end, dim3(nblk(3 * F * N)), dim3(256), 0, s, vhat, vk, d.g1, 3 * F, G, N);
+    hipLaunchKernelGGL(k_zero, dim3(nblk(nD)), dim3(256), 0, s, vbc, nD);
+    if (F > NI) {
+        const int64_t nb = 3 * (F - NI) * G * N;
+        hipLaunchKernelGGL(k_goback, dim3(nblk(nb)), dim3(256), 0, s, d.GB, m->d.cls, d.fl, d.flf, d.fr, d.frf,
+                           g_nodal, g_nodal, vbc, NI, F, F, E, G, N);
+        // boundary part of the iterate = prescribed data
+        for (int c = 0; c < 3; ++c)
+            hipLaunchKernelGGL(k_copyd, dim3(nblk((F - NI) * G * N)), dim3(256), 0, s,
+                               vbc + ((int64_t)c * F + NI) * G * N, vk + ((int64_t)c * F + NI) * G * N,
+                               (F - NI) * G * N);
+    }
+    if (opts->pressure_guess == STDG_GUESS_PREVIOUS)
+        hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, p, pk, nP);
+    else
+        hipLaunchKernelGGL(k_zero, dim3(nblk(nP)), dim3(256), 0, s, pk, nP);
+    STDG_HIP(hipGetLastError());
+    int piters = 0, viters = 0;
+    double pres = 0.0, vres = 0.0;
+    for (int k = 0; k < npic; ++k) {
+        // step 1
+        if (int e = stdg_main_from_dual(m, vk, vbk, s)) return e;
+        hipLaunchKernelGGL(k_dualgrad, dim3(nblk(nD)), dim3(256), 0, s, d.US, d.UN, m->d.cls, d.fl, d.flf, d.fr, d.TW,
+                           pk, dt, wg, F, G, N);
+        hipLaunchKernelGGL(k_average, dim3(nblk(nM)), dim3(256), 0, s, d.A, m->d.cls, d.tet_face, wg, lam, E, F, G, N);
+        // step 2
+        CKP(launch_convection(m, vbk, vbc, ups, s));
+        // step 3
+        hipLaunchKernelGGL(k_visc_rhs, dim3(nblk(nM)), dim3(256), 0, s, d.MIT, d.BB, m->d.cls, m->d.nbr, d.tet_face,
+                           d.g0g1, d.Tm, d.W, vprev, ups, lam, vbc, m->cfg.nu * dt, rhs, E, F, G, N);
+        hipLaunchKernelGGL(k_copyd, dim3(nblk(nM)), dim3(256), 0, s, vbk, vhalf, nM);
+        STDG_HIP(hipGetLastError());
+        int vit = 0;
+        double vrel = 0.0;
+        int e = viscous_solve(m, rhs, vhalf, opts->viscous, kw, s, vit, vrel);
+        if (e < 0) return e;
+        viters += vit;
+        vres = std::max(vres, vrel);
+        // step 4
+        hipLaunchKernelGGL(k_goback, dim3(nblk(3 * NI * G * N)), dim3(256), 0, s, d.GB, m->d.cls, d.fl, d.flf, d.fr,
+                           d.frf, vhalf, vhalf, Fv, (int64_t)0, NI, F, E, G, N);
+        for (int c = 0; c < 3 && F > NI; ++c)
+            hipLaunchKernelGGL(k_copyd, dim3(nblk((F - NI) * G * N)), dim3(256), 0, s,
+                               vbc + ((int64_t)c * F + NI) * G * N, Fv + ((int64_t)c * F + NI) * G * N,
+                               (F - NI) * G * N);
+        // step 5
+        hipLaunchKernelGGL(k_rhs_pressure, dim3(nblk(nP)), dim3(256), 0, s, d.QT, m->d.cls, d.tet_face, d.W, Fv, dt,
+                           bp, E, F, G, N);
+        hipLaunchKernelGGL(k_zero, dim3(nblk(nP)), dim3(256), 0, s, dp, nP);
+        STDG_HIP(hipGetLastError());
+        stdg_solve_report prep;
+        e = stdg_pressure_solve(m, bp, dp, &opts->pressure, &prep, s);
+        if (e < 0) return e;
+        piters += prep.inner_iters;
+        pres = std::max(pres, prep.rel_residual);
+        // step 6
+        hipLaunchKernelGGL(k_dualgrad, dim3(nblk(nD)), dim3(256), 0, s, d.US, d.UN, m->d.cls, d.fl, d.flf, d.fr, d.TW,
+                           dp, dt, wg, F, G, N);
+        hipLaunchKernelGGL(k_update, dim3(nblk(nD)), dim3(256), 0, s, Fv, wg, vk, F, NI, G, N);
+        hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, pk, dp, 1.0, nP);
+        STDG_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_copyd, dim3(nblk(nD)), dim3(256), 0, s, vk, vhat, nD);
+    hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, pk, p, nP);
+    if (int e = stdg_main_from_dual(m, vk, vbar, s)) return e;
+    STDG_HIP(hipStreamSynchronize(s));
+    if (rep) {
+        rep->pressure_iters = piters;
+        rep->viscous_iters = viters;
+        rep->max_pressure_residual = pres;
+        rep->max_viscous_residual = vres;
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return STDG_OK;
+}
