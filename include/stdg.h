@@ -61,6 +61,10 @@ extern "C" {
 #define STDG_AUTO 0            /* CG when p_gamma = 0, GMRES otherwise */
 #define STDG_CG 1
 #define STDG_GMRES 2
+#define STDG_CG_TIME 3         /* any p_gamma: S = dt^2 (S^sp (x) I)(I (x) C), so the  */
+                               /* space-time system is G independent symmetric      */
+                               /* spatial systems (S^sp (x) I) w = b, x = (I (x) C^-1) w */
+                               /* solved by CG: same anchored solution, no GMRES    */
 
 typedef struct stdg_mesh stdg_mesh;
 
@@ -145,7 +149,7 @@ int stdg_pressure_apply_f32(const stdg_mesh* mesh, const float* x, float* y,
                             void* stream);
 
 typedef struct {
-    int32_t method;        /* STDG_AUTO, STDG_CG or STDG_GMRES                */
+    int32_t method;        /* STDG_AUTO, STDG_CG, STDG_GMRES or STDG_CG_TIME  */
     int32_t restart;       /* GMRES restart length m (1..200)                  */
     double rtol;           /* stop at ||b_a - S_a x|| <= rtol ||b_a||          */
     int32_t max_iter;      /* total inner Krylov iterations allowed            */
@@ -207,7 +211,10 @@ typedef struct {
     int32_t viscous_iters;
     double max_pressure_residual;
     double max_viscous_residual;
-    double seconds;
+    double seconds;             /* whole step                                 */
+    double pressure_seconds;    /* inside the pressure-correction solves      */
+    double viscous_seconds;     /* inside the viscous solves                  */
+    int32_t pressure_applies;   /* pressure-operator applications             */
 } stdg_step_report;
 
 /* Defaults: n_picard 0, zero pressure guess, solve defaults, viscous rtol 1e-12. */

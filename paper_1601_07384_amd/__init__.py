@@ -13,10 +13,11 @@ import numpy as np
 from . import _lib
 from ._lib import (Config, MeshInfo, SolveOpts, SolveReport, StepOpts, StepReport, StdgError,
                    STDG_OK, STDG_NOT_CONVERGED, STDG_FP64, STDG_FP32,
-                   STDG_AUTO, STDG_CG, STDG_GMRES, STDG_GUESS_ZERO, STDG_GUESS_PREVIOUS)
+                   STDG_AUTO, STDG_CG, STDG_GMRES, STDG_CG_TIME, STDG_GUESS_ZERO,
+                   STDG_GUESS_PREVIOUS)
 
 __all__ = ["Mesh", "StdgError", "STDG_FP64", "STDG_FP32", "STDG_AUTO",
-           "STDG_CG", "STDG_GMRES", "STDG_GUESS_ZERO", "STDG_GUESS_PREVIOUS",
+           "STDG_CG", "STDG_GMRES", "STDG_CG_TIME", "STDG_GUESS_ZERO", "STDG_GUESS_PREVIOUS",
            "solve_opts", "step_opts"]
 
 

@@ -22,6 +22,7 @@ STDG_FP32 = 1
 STDG_AUTO = 0
 STDG_CG = 1
 STDG_GMRES = 2
+STDG_CG_TIME = 3
 
 
 class Config(ctypes.Structure):
@@ -65,7 +66,9 @@ class StepOpts(ctypes.Structure):
 class StepReport(ctypes.Structure):
     _fields_ = [("pressure_iters", ctypes.c_int32), ("viscous_iters", ctypes.c_int32),
                 ("max_pressure_residual", ctypes.c_double),
-                ("max_viscous_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("max_viscous_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("pressure_seconds", ctypes.c_double), ("viscous_seconds", ctypes.c_double),
+                ("pressure_applies", ctypes.c_int32)]
 
 
 # (name, restype, argtypes) of every symbol declared in include/stdg.h

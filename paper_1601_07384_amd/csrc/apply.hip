@@ -270,6 +270,44 @@ static hipError_t launch_apply(const stdg_mesh* m, const T* BT, const T* C, cons
     return launch_rows<T>(m, BT, C, x, y, s);
 }
 
+hipError_t launch_apply_f64_c(const stdg_mesh* m, const double* C, const double* x, double* y,
+                              hipStream_t s) {
+    return launch_apply<double>(m, m->d.blocks, C, x, y, s);
+}
+
+hipError_t launch_apply_f32_c(const stdg_mesh* m, const float* C, const float* x, float* y, hipStream_t s) {
+    return launch_apply<float>(m, m->d.blocks32, C, x, y, s);
+}
+
+// y[e][a][n] = sum_b M[a][b] x[e][b][n]  (time mixing)
+template <typename T>
+__global__ void k_tmix(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ M, int64_t E,
+                       int G, int N) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= E * N) return;
+    const int64_t e = t / N;
+    const int n = (int)(t - e * N);
+    T v[8];
+    for (int b = 0; b < G; ++b) v[b] = x[(e * G + b) * N + n];
+    for (int a = 0; a < G; ++a) {
+        T s = T(0);
+        for (int b = 0; b < G; ++b) s += M[a * G + b] * v[b];
+        y[(e * G + a) * N + n] = s;
+    }
+}
+
+hipError_t time_mix_f64(const stdg_mesh* m, const double* M, const double* x, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_tmix<double>, dim3((unsigned)((m->E * m->N + 255) / 256)), dim3(256), 0, s, x, y, M,
+                       m->E, m->G, m->N);
+    return hipGetLastError();
+}
+
+hipError_t time_mix_f32(const stdg_mesh* m, const float* M, const float* x, float* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_tmix<float>, dim3((unsigned)((m->E * m->N + 255) / 256)), dim3(256), 0, s, x, y, M,
+                       m->E, m->G, m->N);
+    return hipGetLastError();
+}
+
 hipError_t launch_apply_f64(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
     return launch_apply<double>(m, m->d.blocks, m->d.C, x, y, s);
 }

@@ -42,12 +42,30 @@ int upload_tables(stdg_mesh* m) {
     STDG_HIP(hipMemcpy(m->d.nbr, m->nbr.data(), 4 * m->E * sizeof(int32_t), hipMemcpyHostToDevice));
     STDG_HIP(hipMemcpy(m->d.C, m->Ctime.data(), m->G * m->G * sizeof(double), hipMemcpyHostToDevice));
     STDG_HIP(hipMemcpy(m->d.C32, c32.data(), m->G * m->G * sizeof(float), hipMemcpyHostToDevice));
+    {
+        const int G = m->G;
+        std::vector<real> ci(m->Ctime.begin(), m->Ctime.end());
+        lu_inverse(G, ci);
+        std::vector<double> cinv(G * G), cid(G * G, 0.0);
+        std::vector<float> cinv32(G * G), cid32(G * G, 0.0f);
+        for (int i = 0; i < G * G; ++i) { cinv[i] = (double)ci[i]; cinv32[i] = (float)ci[i]; }
+        for (int i = 0; i < G; ++i) { cid[i * G + i] = 1.0; cid32[i * G + i] = 1.0f; }
+        STDG_HIP(hipMalloc(&m->d.Cinv, G * G * sizeof(double)));
+        STDG_HIP(hipMalloc(&m->d.Cinv32, G * G * sizeof(float)));
+        STDG_HIP(hipMalloc(&m->d.Cid, G * G * sizeof(double)));
+        STDG_HIP(hipMalloc(&m->d.Cid32, G * G * sizeof(float)));
+        STDG_HIP(hipMemcpy(m->d.Cinv, cinv.data(), G * G * sizeof(double), hipMemcpyHostToDevice));
+        STDG_HIP(hipMemcpy(m->d.Cinv32, cinv32.data(), G * G * sizeof(float), hipMemcpyHostToDevice));
+        STDG_HIP(hipMemcpy(m->d.Cid, cid.data(), G * G * sizeof(double), hipMemcpyHostToDevice));
+        STDG_HIP(hipMemcpy(m->d.Cid32, cid32.data(), G * G * sizeof(float), hipMemcpyHostToDevice));
+    }
     return STDG_OK;
 }
 
 void free_tables(stdg_mesh* m) {
     for (void* p : {(void*)m->d.blocks, (void*)m->d.blocks32, (void*)m->d.cls, (void*)m->d.nbr,
-                    (void*)m->d.C, (void*)m->d.C32})
+                    (void*)m->d.C, (void*)m->d.C32, (void*)m->d.Cinv, (void*)m->d.Cinv32,
+                    (void*)m->d.Cid, (void*)m->d.Cid32})
         if (p) (void)hipFree(p);
     m->d = DeviceTables();
 }

@@ -37,6 +37,10 @@ struct DeviceTables {
     int32_t* nbr = nullptr;       // [E][4]  -1 on a boundary face
     double* C = nullptr;          // [G][G]  time factor W T^-1 W
     float* C32 = nullptr;
+    double* Cinv = nullptr;       // [G][G]  its inverse
+    float* Cinv32 = nullptr;
+    double* Cid = nullptr;        // [G][G]  identity (spatial operator on every time node)
+    float* Cid32 = nullptr;
 };
 
 // Krylov workspaces (allocated on first solve, sized for the mesh).

@@ -334,14 +334,26 @@ struct Ctx {
 };
 
 template <typename T> struct Apply;
+// op 0: S = B (x) C; op 1: viscous operator; op 2: B (x) I (the spatial
+// pressure operator on every time node, B = dt^2 S^sp).
 template <> struct Apply<double> {
     static hipError_t run(const Ctx& c, const double* x, double* y) {
-        return c.op == 0 ? launch_apply_f64(c.m, x, y, c.s) : launch_visc_apply(c.m, x, y, c.s);
+        if (c.op == 0) return launch_apply_f64(c.m, x, y, c.s);
+        if (c.op == 2) return launch_apply_f64_c(c.m, c.m->d.Cid, x, y, c.s);
+        return launch_visc_apply(c.m, x, y, c.s);
+    }
+    static hipError_t tmix(const Ctx& c, bool inverse, const double* x, double* y) {
+        return time_mix_f64(c.m, inverse ? c.m->d.Cinv : c.m->d.C, x, y, c.s);
     }
 };
 template <> struct Apply<float> {
     static hipError_t run(const Ctx& c, const float* x, float* y) {
-        return c.op == 0 ? launch_apply_f32(c.m, x, y, c.s) : hipErrorInvalidValue;
+        if (c.op == 0) return launch_apply_f32(c.m, x, y, c.s);
+        if (c.op == 2) return launch_apply_f32_c(c.m, c.m->d.Cid32, x, y, c.s);
+        return hipErrorInvalidValue;
+    }
+    static hipError_t tmix(const Ctx& c, bool inverse, const float* x, float* y) {
+        return time_mix_f32(c.m, inverse ? c.m->d.Cinv32 : c.m->d.C32, x, y, c.s);
     }
 };
 
@@ -465,6 +477,18 @@ template <typename T>
 int run_krylov(Ctx& c, int method, const T* b, T* x, T* r, T* p, T* q, T* V, int mres, double tol_abs,
                int max_it, int check_every, int& iters, double& res) {
     if (method == STDG_CG) return cg<T>(c, b, x, r, p, q, tol_abs, max_it, check_every, iters, res);
+    if (method == STDG_CG_TIME && c.op == 0) {
+        // S x = b  <=>  (B (x) I) w = b with w = (I (x) C) x; the residual is the same vector
+        CK(Apply<T>::tmix(c, false, x, q));
+        hipLaunchKernelGGL(k_copy<T>, dim3(grid_for(c.n)), dim3(256), 0, c.s, q, x, c.n);
+        c.op = 2;
+        const int st = cg<T>(c, b, x, r, p, q, tol_abs, max_it, check_every, iters, res);
+        c.op = 0;
+        CK(Apply<T>::tmix(c, true, x, q));
+        hipLaunchKernelGGL(k_copy<T>, dim3(grid_for(c.n)), dim3(256), 0, c.s, q, x, c.n);
+        CK(hipGetLastError());
+        return st;
+    }
     return gmres<T>(c, b, x, r, V, mres, tol_abs, max_it, check_every, iters, res);
 }
 
@@ -589,7 +613,14 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
     if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
     stdg_solve_opts o = *opts;
     if (o.method == STDG_AUTO) o.method = (m->G == 1) ? STDG_CG : STDG_GMRES;
-    if (o.method != STDG_CG && o.method != STDG_GMRES) { set_error("unknown method"); return STDG_ERR_ARG; }
+    if (o.method != STDG_CG && o.method != STDG_GMRES && o.method != STDG_CG_TIME) {
+        set_error("unknown method");
+        return STDG_ERR_ARG;
+    }
+    if (o.method == STDG_CG && m->G > 1) {
+        set_error("CG needs p_gamma = 0 (the space-time operator is not symmetric); use STDG_CG_TIME");
+        return STDG_ERR_ARG;
+    }
     if (o.method == STDG_GMRES && (o.restart < 1 || o.restart > 200)) { set_error("restart out of range"); return STDG_ERR_ARG; }
     if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1) { set_error("bad tolerance/iteration options"); return STDG_ERR_ARG; }
     if (o.precision != STDG_FP64 && o.precision != STDG_FP32) { set_error("bad precision"); return STDG_ERR_ARG; }

@@ -532,8 +532,8 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     else
         hipLaunchKernelGGL(k_zero, dim3(nblk(nP)), dim3(256), 0, s, pk, nP);
     STDG_HIP(hipGetLastError());
-    int piters = 0, viters = 0;
-    double pres = 0.0, vres = 0.0;
+    int piters = 0, viters = 0, papplies = 0;
+    double pres = 0.0, vres = 0.0, psec = 0.0, vsec = 0.0;
     for (int k = 0; k < npic; ++k) {
         // step 1
         if (int e = stdg_main_from_dual(m, vk, vbk, s)) return e;
@@ -549,8 +549,12 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         STDG_HIP(hipGetLastError());
         int vit = 0;
         double vrel = 0.0;
+        STDG_HIP(hipStreamSynchronize(s));
+        auto tv0 = std::chrono::steady_clock::now();
         int e = viscous_solve(m, rhs, vhalf, opts->viscous, kw, s, vit, vrel);
         if (e < 0) return e;
+        STDG_HIP(hipStreamSynchronize(s));
+        vsec += std::chrono::duration<double>(std::chrono::steady_clock::now() - tv0).count();
         viters += vit;
         vres = std::max(vres, vrel);
         // step 4
@@ -566,9 +570,12 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         hipLaunchKernelGGL(k_zero, dim3(nblk(nP)), dim3(256), 0, s, dp, nP);
         STDG_HIP(hipGetLastError());
         stdg_solve_report prep;
+        STDG_HIP(hipStreamSynchronize(s));
         e = stdg_pressure_solve(m, bp, dp, &opts->pressure, &prep, s);
         if (e < 0) return e;
         piters += prep.inner_iters;
+        papplies += prep.applies;
+        psec += prep.seconds;
         pres = std::max(pres, prep.rel_residual);
         // step 6
         hipLaunchKernelGGL(k_dualgrad, dim3(nblk(nD)), dim3(256), 0, s, d.US, d.UN, m->d.cls, d.fl, d.flf, d.fr, d.TW,
@@ -587,6 +594,9 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         rep->max_pressure_residual = pres;
         rep->max_viscous_residual = vres;
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        rep->pressure_seconds = psec;
+        rep->viscous_seconds = vsec;
+        rep->pressure_applies = papplies;
     }
     return STDG_OK;
 }
