@@ -66,6 +66,7 @@ void taylor_eval(const std::vector<std::array<int, 3>>& ex, const V3& x, const V
 // local face f, row-major N x N blocks (see picard_tables.cpp).
 struct PicardTables {
     std::vector<double> A, GB, QT, US, UN, BB, SV, MI;
+    std::vector<double> DV;        // [C][NG][NG] inverse viscous diagonal block, column-major
     int qs = 0, qt = 0, qv = 0, nqf = 0, nqv = 0;
     std::vector<double> cJinv, cdet, cnrm, PHf, PHn, FW, PHv, dPHv, wv, tq, tw, gq;
     std::vector<double> Tm, TW, W, g0g1, g1;
@@ -73,7 +74,8 @@ struct PicardTables {
 
 struct PicardDevice {
     double *A = nullptr, *GB = nullptr, *QT = nullptr, *US = nullptr, *UN = nullptr, *BB = nullptr;
-    double *SVT = nullptr, *MIT = nullptr;
+    double *SVT = nullptr, *MIT = nullptr, *DV = nullptr;
+    double *SVt = nullptr, *MIt = nullptr;   // blocks transposed (column-major) for the fast kernel
     double *cJinv = nullptr, *cdet = nullptr, *cnrm = nullptr, *PHf = nullptr, *PHn = nullptr, *FW = nullptr;
     double *PHv = nullptr, *dPHv = nullptr, *wv = nullptr, *tq = nullptr, *tw = nullptr, *gq = nullptr;
     double *Tm = nullptr, *TW = nullptr, *W = nullptr, *g0g1 = nullptr, *g1 = nullptr;

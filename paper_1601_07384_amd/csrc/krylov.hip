@@ -329,7 +329,9 @@ struct Ctx {
     double* scal;
     double* hscal;
     double* gm;        // GMRES small arrays: H, g, cs, sn, y, h
-    int op = 0;        // 0: pressure Schur operator, 1: viscous operator (3 components)
+    int op = 0;        // 0: pressure Schur operator, 1: viscous operator (3 components),
+                       // 2: B (x) I, 3: block-Jacobi preconditioned viscous operator D^-1 A
+    double* tmp = nullptr;   // op 3: holds A x before D^-1
     int applies = 0;
 };
 
@@ -340,6 +342,10 @@ template <> struct Apply<double> {
     static hipError_t run(const Ctx& c, const double* x, double* y) {
         if (c.op == 0) return launch_apply_f64(c.m, x, y, c.s);
         if (c.op == 2) return launch_apply_f64_c(c.m, c.m->d.Cid, x, y, c.s);
+        if (c.op == 3) {
+            const hipError_t e = launch_visc_apply(c.m, x, c.tmp, c.s);
+            return e != hipSuccess ? e : launch_visc_precond(c.m, c.tmp, y, c.s);
+        }
         return launch_visc_apply(c.m, x, y, c.s);
     }
     static hipError_t tmix(const Ctx& c, bool inverse, const double* x, double* y) {
@@ -534,7 +540,10 @@ void free_workspace(stdg_mesh* m) {
 
 // Plain (non-singular) solve A_v x = b of the viscous system with the
 // library's CG/GMRES; x holds the guess.  Vectors [3][E][G][N]; work vectors
-// are taken from `work` (needs (restart + 4) * n doubles for GMRES, 4 n for CG).
+// are taken from `work` ((restart + 6) * n doubles).  GMRES runs on the
+// left block-Jacobi preconditioned system D^-1 A x = D^-1 b, D the exact
+// space-time diagonal block of each element; convergence is judged on the
+// true residual of A x = b.
 int viscous_solve(stdg_mesh* m, const double* b, double* x, const stdg_solve_opts& o, double* work,
                   hipStream_t s, int& iters, double& rel) {
     if (int e = ensure_workspace(m, 0, false)) return e;
@@ -552,7 +561,12 @@ int viscous_solve(stdg_mesh* m, const double* b, double* x, const stdg_solve_opt
     double* pp = work + n;
     double* q = work + 2 * n;
     double* V = work + 3 * n;
-    const int method = o.method == STDG_AUTO ? (m->G == 1 ? STDG_CG : STDG_GMRES) : o.method;
+    const int method = o.method == STDG_AUTO ? STDG_GMRES : o.method;
+    const bool pre = method == STDG_GMRES;
+    if (method == STDG_GMRES && o.restart < 1) { set_error("viscous GMRES restart must be >= 1"); return STDG_ERR_ARG; }
+    if (method != STDG_GMRES && method != STDG_CG) { set_error("viscous method must be CG or GMRES"); return STDG_ERR_ARG; }
+    double* bp = work + (int64_t)(o.restart + 5) * n;
+    c.tmp = work + (int64_t)(o.restart + 4) * n;
     hipLaunchKernelGGL((k_dot<double, double>), dim3(NBLK), dim3(RT), 0, s, b, b, n, c.partial);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, c.partial, NBLK, c.scal, (int)S_BN2, (int)FIN_STORE);
     double bn2;
@@ -566,13 +580,24 @@ int viscous_solve(stdg_mesh* m, const double* b, double* x, const stdg_solve_opt
         return STDG_OK;
     }
     double tol = o.rtol * bn;
+    const double* rhs = b;
+    if (pre) {
+        CK(launch_visc_precond(m, b, bp, s));
+        hipLaunchKernelGGL((k_dot<double, double>), dim3(NBLK), dim3(RT), 0, s, bp, bp, n, c.partial);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, c.partial, NBLK, c.scal, (int)S_BN2, (int)FIN_STORE);
+        double pn2;
+        if (int e = read_scal(c, S_BN2, pn2)) return e;
+        tol = o.rtol * std::sqrt(pn2);
+        rhs = bp;
+        c.op = 3;
+    }
     int status = STDG_OK;
     for (int round = 0; round < 6; ++round) {
         int it = 0;
         double res = 0.0;
         const int left = o.max_iter - iters;
         if (left <= 0) { status = STDG_NOT_CONVERGED; break; }
-        status = run_krylov<double>(c, method, b, x, r, pp, q, V, o.restart, tol, left, o.check_every, it, res);
+        status = run_krylov<double>(c, method, rhs, x, r, pp, q, V, o.restart, tol, left, o.check_every, it, res);
         iters += it;
         if (status < 0) return status;
         // true residual
@@ -584,7 +609,7 @@ int viscous_solve(stdg_mesh* m, const double* b, double* x, const stdg_solve_opt
         rel = std::sqrt(rn2) / bn;
         if (rel <= o.rtol) { status = STDG_OK; break; }
         if (status == STDG_NOT_CONVERGED) break;
-        tol *= 0.25;
+        tol *= std::min(0.25, std::max(1e-4, 0.5 * o.rtol / rel));
     }
     return status;
 }

@@ -233,6 +233,109 @@ __global__ void k_visc_apply(const double* __restrict__ SV, const double* __rest
     y[t] = s;
 }
 
+// Viscous operator, fast form: one thread per (component, element, time node
+// a) with the same class-uniform wavefronts as the pressure kernel (block
+// columns through scalar loads, blocks stored column-major):
+//   y_a = nu dt W_a sum_k SV_k x_k[a] + MI sum_b T_ab x_i[b].
+template <int N, int G>
+__global__ void __launch_bounds__(256) k_visc_tn(
+    const double* __restrict__ SVt, const double* __restrict__ MIt, const int32_t* __restrict__ cls,
+    const int32_t* __restrict__ nbr, const double* __restrict__ Tm, const double* __restrict__ W, double nu_dt,
+    const double* __restrict__ x, double* __restrict__ y, int64_t E) {
+    const int64_t nbE = (E + 255) / 256;
+    const int a = (int)(blockIdx.x % G);
+    const int64_t rest = blockIdx.x / G;
+    const int comp = (int)(rest / nbE);
+    const int64_t i = (rest % nbE) * 256 + threadIdx.x;
+    const bool valid = i < E;
+    const int64_t ii = valid ? i : E - 1;
+    const int c = cls[ii];
+    const int c0 = __builtin_amdgcn_readfirstlane(c);
+    const bool uniform = __all(c == c0);
+    const double* xc = x + (int64_t)comp * E * G * N;
+    const double wa = nu_dt * W[a];
+    double Ta[G];
+#pragma unroll
+    for (int b = 0; b < G; ++b) Ta[b] = Tm[a * G + b];
+    double acc[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) acc[r] = 0.0;
+    int nb[5];
+    nb[0] = (int)ii;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) nb[f + 1] = nbr[4 * ii + f];
+    if (uniform) {
+        const double* Bc = SVt + (int64_t)c0 * 5 * N * N;
+        for (int k = 0; k < 5; ++k) {
+            const int t = nb[k];
+            if (__builtin_amdgcn_readfirstlane(t) < 0) continue;
+            const double* xt = xc + ((int64_t)t * G + a) * N;
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const double xp = wa * xt[m];
+                const double* col = Bc + k * N * N + m * N;
+#pragma unroll
+                for (int r = 0; r < N; ++r) acc[r] += col[r] * xp;
+            }
+        }
+        const double* Mc = MIt + (int64_t)c0 * N * N;
+        const double* xi = xc + (int64_t)ii * G * N;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            double xp = 0.0;
+#pragma unroll
+            for (int b = 0; b < G; ++b) xp += Ta[b] * xi[b * N + m];
+            const double* col = Mc + m * N;
+#pragma unroll
+            for (int r = 0; r < N; ++r) acc[r] += col[r] * xp;
+        }
+    } else {
+        const double* Bc = SVt + (int64_t)c * 5 * N * N;
+        for (int k = 0; k < 5; ++k) {
+            const int t = nb[k];
+            if (t < 0) continue;
+            const double* xt = xc + ((int64_t)t * G + a) * N;
+            for (int m = 0; m < N; ++m) {
+                const double xp = wa * xt[m];
+                const double* col = Bc + k * N * N + m * N;
+#pragma unroll
+                for (int r = 0; r < N; ++r) acc[r] += col[r] * xp;
+            }
+        }
+        const double* Mc = MIt + (int64_t)c * N * N;
+        const double* xi = xc + (int64_t)ii * G * N;
+        for (int m = 0; m < N; ++m) {
+            double xp = 0.0;
+#pragma unroll
+            for (int b = 0; b < G; ++b) xp += Ta[b] * xi[b * N + m];
+            const double* col = Mc + m * N;
+#pragma unroll
+            for (int r = 0; r < N; ++r) acc[r] += col[r] * xp;
+        }
+    }
+    if (valid) {
+        double* yi = y + (int64_t)comp * E * G * N + (i * G + a) * N;
+#pragma unroll
+        for (int r = 0; r < N; ++r) yi[r] = acc[r];
+    }
+}
+
+// y_i = D_i^-1 x_i for the viscous diagonal blocks (per component), DV
+// column-major so that the threads of one element read consecutive values.
+__global__ void k_blockdiag(const double* __restrict__ DV, const int32_t* __restrict__ cls,
+                            const double* __restrict__ x, double* __restrict__ y, int64_t E, int NG) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * E * NG) return;
+    const int row = (int)(t % NG);
+    const int64_t ce = t / NG;                 // comp * E + element
+    const int64_t i = ce % E;
+    const double* D = DV + (int64_t)cls[i] * NG * NG + row;
+    const double* xi = x + ce * NG;
+    double s = 0.0;
+    for (int col = 0; col < NG; ++col) s += D[(int64_t)col * NG] * xi[col];
+    y[t] = s;
+}
+
 // Space-time DG convection with the Rusanov flux (eq. convdg), one block of
 // 64 threads per element.  For each time point of the rule: the lanes first
 // evaluate the velocity at the volume points (flux tensor pulled back by the
@@ -384,11 +487,34 @@ int upload(T*& dst, const std::vector<T>& src) {
 
 }  // namespace
 
+template <int N, int G>
+static hipError_t launch_visc_ng(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
+    const PicardDevice& d = m->pd;
+    const int64_t blocks = (m->E + 255) / 256 * G * 3;
+    hipLaunchKernelGGL((k_visc_tn<N, G>), dim3((unsigned)blocks), dim3(256), 0, s, d.SVt, d.MIt, m->d.cls,
+                       m->d.nbr, d.Tm, d.W, m->cfg.nu * m->cfg.dt, x, y, m->E);
+    return hipGetLastError();
+}
+
 hipError_t launch_visc_apply(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
+#define STDG_VN(n, g) \
+    if (m->N == n && m->G == g) return launch_visc_ng<n, g>(m, x, y, s);
+    STDG_VN(4, 1) STDG_VN(4, 2) STDG_VN(4, 3) STDG_VN(4, 4) STDG_VN(4, 5)
+    STDG_VN(10, 1) STDG_VN(10, 2) STDG_VN(10, 3) STDG_VN(10, 4) STDG_VN(10, 5)
+    STDG_VN(20, 1) STDG_VN(20, 2) STDG_VN(20, 3) STDG_VN(20, 4) STDG_VN(20, 5)
+    STDG_VN(35, 1) STDG_VN(35, 2) STDG_VN(35, 3) STDG_VN(35, 4) STDG_VN(35, 5)
+#undef STDG_VN
     const PicardDevice& d = m->pd;
     const int64_t n = 3 * m->E * m->Nst;
     hipLaunchKernelGGL(k_visc_apply, dim3(nblk(n)), dim3(256), 0, s, d.SVT, d.MIT, m->d.cls, m->d.nbr, d.Tm, d.W,
                        m->cfg.nu * m->cfg.dt, x, y, m->E, m->G, m->N);
+    return hipGetLastError();
+}
+
+hipError_t launch_visc_precond(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
+    const int NG = m->Nst;
+    const int64_t n = 3 * m->E * NG;
+    hipLaunchKernelGGL(k_blockdiag, dim3(nblk(n)), dim3(256), 0, s, m->pd.DV, m->d.cls, x, y, m->E, NG);
     return hipGetLastError();
 }
 
@@ -403,6 +529,18 @@ int upload_picard_tables(stdg_mesh* m) {
              {&d.wv, &t.wv}, {&d.tq, &t.tq}, {&d.tw, &t.tw}, {&d.gq, &t.gq}, {&d.Tm, &t.Tm}, {&d.TW, &t.TW},
              {&d.W, &t.W}, {&d.g0g1, &t.g0g1}, {&d.g1, &t.g1}})
         if ((e = upload(*pr.first, *pr.second))) return e;
+    {
+        const int N = m->N;
+        const size_t NN = (size_t)N * N;
+        std::vector<double> svt(t.SV.size()), mit(t.MI.size());
+        for (size_t blk = 0; blk < t.SV.size() / NN; ++blk)
+            for (int r = 0; r < N; ++r)
+                for (int c = 0; c < N; ++c) svt[blk * NN + (size_t)c * N + r] = t.SV[blk * NN + (size_t)r * N + c];
+        for (size_t blk = 0; blk < t.MI.size() / NN; ++blk)
+            for (int r = 0; r < N; ++r)
+                for (int c = 0; c < N; ++c) mit[blk * NN + (size_t)c * N + r] = t.MI[blk * NN + (size_t)r * N + c];
+        if ((e = upload(d.SVt, svt)) || (e = upload(d.MIt, mit)) || (e = upload(d.DV, t.DV))) return e;
+    }
     const int64_t F = (int64_t)m->faces.size();
     std::vector<int64_t> fl(F), fr(F);
     std::vector<int32_t> flf(F), frf(F);
@@ -422,7 +560,8 @@ void free_picard(stdg_mesh* m) {
                     (void*)d.MIT, (void*)d.cJinv, (void*)d.cdet, (void*)d.cnrm, (void*)d.PHf, (void*)d.PHn,
                     (void*)d.FW, (void*)d.PHv, (void*)d.dPHv, (void*)d.wv, (void*)d.tq, (void*)d.tw, (void*)d.gq,
                     (void*)d.Tm, (void*)d.TW, (void*)d.W, (void*)d.g0g1, (void*)d.g1, (void*)d.tet_face,
-                    (void*)d.fl, (void*)d.fr, (void*)d.flf, (void*)d.frf, (void*)d.work})
+                    (void*)d.fl, (void*)d.fr, (void*)d.flf, (void*)d.frf, (void*)d.work, (void*)d.DV,
+                    (void*)d.SVt, (void*)d.MIt})
         if (p) (void)hipFree(p);
     d = PicardDevice();
 }
@@ -489,8 +628,8 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     const int G = m->G, N = m->N;
     const int64_t nD = 3 * F * G * N, nM = 3 * E * G * N, nP = E * G * N;
     const int mres = std::max(1, opts->viscous.restart);
-    // workspace: 4 dual + 6 main + 3 pressure vectors + viscous Krylov (mres + 4) main
-    const size_t need = 4 * nD + 6 * nM + 3 * nP + (size_t)(mres + 4) * nM;
+    // workspace: 4 dual + 6 main + 3 pressure vectors + viscous Krylov (mres + 6) main
+    const size_t need = 4 * nD + 6 * nM + 3 * nP + (size_t)(mres + 6) * nM;
     PicardDevice& d = m->pd;
     if (d.work_len < need) {
         if (d.work) STDG_HIP(hipFree(d.work));

@@ -307,6 +307,30 @@ int build_picard_tables(stdg_mesh* m, const std::vector<int64_t>& rep) {
     lu_inverse(G, Ti);
     for (int a = 0; a < G; ++a)
         for (int b = 0; b < G; ++b) t.TW[a * G + b] = (double)(Ti[a * G + b] * Wd[b]);
+    // inverse of the viscous diagonal block D = MI (x) T + nu dt SV0 (x) W per class
+    {
+        const int NG = N * G;
+        const real nudt = (real)m->cfg.nu * (real)m->cfg.dt;
+        t.DV.assign((size_t)C * NG * NG, 0);
+        int badv = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : badv)
+        for (int c = 0; c < C; ++c) {
+            std::vector<real> D((size_t)NG * NG, 0);
+            for (int a = 0; a < G; ++a)
+                for (int r = 0; r < N; ++r)
+                    for (int b = 0; b < G; ++b)
+                        for (int mm = 0; mm < N; ++mm) {
+                            real v = (real)t.MI[(size_t)c * NN + r * N + mm] * T[a * G + b];
+                            if (a == b) v += nudt * (real)t.SV[(size_t)c * 5 * NN + r * N + mm] * Wd[a];
+                            D[(size_t)(a * N + r) * NG + b * N + mm] = v;
+                        }
+            if (!lu_inverse(NG, D)) { badv++; continue; }
+            for (int row = 0; row < NG; ++row)
+                for (int col = 0; col < NG; ++col)
+                    t.DV[(size_t)c * NG * NG + (size_t)col * NG + row] = (double)D[(size_t)row * NG + col];
+        }
+        if (badv) { set_error("singular viscous diagonal block"); return STDG_ERR_MESH; }
+    }
     // convection time rule
     std::vector<real> tq, tw;
     gauss_legendre01(t.qt, tq, tw);

@@ -1,6 +1,6 @@
 """Per-kernel summary (calls, total, average, share) of a rocprofv3 rocpd database.
 
-Usage: python profiles/summarize_rocpd.py <results.db> [top_n]
+Usage: python -m paper_1601_07384_amd.rocpd_summary <results.db> [top_n]
 """
 import sqlite3
 import sys
