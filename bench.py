@@ -134,7 +134,6 @@ def main():
         vh, vbb, pp = (t.clone() for t in state)
         plain_rep = m.picard_step(vh, vbb, pp, None, opts=plain)
         torch.cuda.synchronize()
-        err_v = float((vh - state[0]).abs().max())   # placeholder, overwritten below
         # compare with the first chosen step from the same state
         vh2, vbb2, pp2 = (t.clone() for t in state)
         m.picard_step(vh2, vbb2, pp2, None, opts=chosen)
