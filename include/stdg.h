@@ -167,6 +167,7 @@ typedef struct {
     int32_t applies;       /* operator applications                            */
     double rel_residual;   /* ||b_a - S_a x|| / ||b_a|| in FP64 at exit        */
     double seconds;        /* wall time of the call                            */
+    double initial_rel_residual;  /* the same for the initial guess            */
 } stdg_solve_report;
 
 /* Fill opts with defaults: AUTO, restart 50, rtol 1e-10, max_iter 20000,
@@ -199,11 +200,35 @@ int stdg_pressure_solve(const stdg_mesh* mesh, const double* b, double* x,
 #define STDG_GUESS_ZERO 0       /* p^{n+1,0} = 0 (the paper's choice)        */
 #define STDG_GUESS_PREVIOUS 1   /* p^{n+1,0} = previous slab's pressure      */
 
+/* Krylov initial guess of the first pressure-correction solve of a step.
+ * That solve yields the first Picard pressure p^{n+1,1} (its unknown is the
+ * correction to p^{n+1,0}); the guesses below predict p^{n+1,1} from the same
+ * quantity of the two previous steps, h0 = p^{n,1} and h1 = p^{n-1,1}, kept
+ * by the caller in `hist`.  Later Picard iterations start from zero.        */
+#define STDG_KRYLOV_ZERO 0         /* zero correction                         */
+#define STDG_KRYLOV_PREVIOUS 1     /* h0                                      */
+#define STDG_KRYLOV_EXTRAPOLATE 2  /* 2 h0 - h1                               */
+#define STDG_KRYLOV_LEARNED 3      /* 2 h0 - h1 + s_D * MLP(features of h0,   */
+                                   /* h1, b),                                 */
+                                   /* see the model section below            */
+
+typedef struct stdg_model stdg_model;
+
 typedef struct {
     int32_t n_picard;           /* Picard iterations; 0 = p_gamma + 1        */
     int32_t pressure_guess;     /* STDG_GUESS_ZERO or STDG_GUESS_PREVIOUS    */
     stdg_solve_opts pressure;   /* pressure-correction solves (eq. A2_mod)   */
     stdg_solve_opts viscous;    /* viscous solves (eq. A1_mod), FP64 only    */
+    int32_t krylov_guess;       /* STDG_KRYLOV_*                              */
+    stdg_model* model;          /* STDG_KRYLOV_LEARNED: the trained model     */
+    double* hist;               /* device [2][E][G][N] or NULL (needed by all */
+                                /* guesses but ZERO): on entry (h0, h1), on   */
+                                /* exit (p^{n+1,1}, h0); zeros before the     */
+                                /* first step                                 */
+    double* rec_b;              /* device [E][G][N] or NULL: receives the     */
+                                /* right-hand side of the first pressure solve */
+    double* rec_x;              /* device [E][G][N] or NULL: receives         */
+                                /* p^{n+1,1} (training data for the model)    */
 } stdg_step_opts;
 
 typedef struct {
@@ -215,9 +240,13 @@ typedef struct {
     double pressure_seconds;    /* inside the pressure-correction solves      */
     double viscous_seconds;     /* inside the viscous solves                  */
     int32_t pressure_applies;   /* pressure-operator applications             */
+    int32_t first_pressure_iters;      /* iterations of the first solve       */
+    double first_pressure_seconds;     /* its time, guess included            */
+    double first_initial_residual;     /* ||b - S x0|| / ||b|| of its guess   */
 } stdg_step_report;
 
-/* Defaults: n_picard 0, zero pressure guess, solve defaults, viscous rtol 1e-12. */
+/* Defaults: n_picard 0, zero pressure guess, solve defaults, viscous rtol
+ * 1e-12, zero Krylov guess, no model, no recording. */
 void stdg_step_opts_default(stdg_step_opts* opts);
 
 /* Advance one slab.  vhat [3][F][G][N]: dual velocity of slab n on entry, of
@@ -247,6 +276,94 @@ int stdg_main_from_dual(const stdg_mesh* mesh, const double* vhat, double* vbar,
  * Asynchronous. */
 int stdg_divergence(const stdg_mesh* mesh, const double* vhat, double* div,
                     void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned Krylov initial guess.
+ *
+ * The first pressure-correction solve of a step (Sec. 2.6, step 5, after the
+ * zero pressure guess of step 0) yields p^{n+1,1}; plain Krylov starts it
+ * from zero or from the previous step's value.  With P = p^{n,1} and
+ * Pm = p^{n-1,1} (the same quantity one and two steps back) and b the
+ * solve's right-hand side, the model corrects the linear extrapolation,
+ * element by element:
+ *     x0 = 2 P - Pm + s_D * MLP(f_i),
+ * f_i (11 N_st + 4 values) = P of element i and of its neighbours across
+ * local faces 0..3 (face f opposite local vertex f) divided by s_P; P - Pm
+ * of the same five elements divided by s_D; b_i divided by s_B; four
+ * neighbour-present flags (missing neighbours give zeros).  s_P, s_D, s_B are
+ * the RMS values of P, P - Pm, b over the mesh (1 if zero).  The MLP
+ * is affine - SiLU - affine - SiLU - affine with `hidden` units; parameters
+ * flat in the order W1 [n_in][hidden], b1, W2 [hidden][hidden], b2,
+ * W3 [hidden][n_out], b3 (n_out = N_st).  Training minimises the mean squared
+ * error against (x* - 2P + Pm) / s_D with Adam, x* = p^{n+1,1}.  The Krylov solve that follows is
+ * unchanged and judges the guess: a poor guess costs iterations, never
+ * accuracy.  A model belongs to one mesh shape (E, N_st); its calls run on
+ * the given stream and must not overlap on one model.
+ */
+typedef struct {
+    int32_t hidden;            /* units per hidden layer (default 128)        */
+    int32_t precision;         /* STDG_FP32 (default) or STDG_FP64            */
+    int32_t batch;             /* rows per training mini-batch and per        */
+                               /* inference chunk (default 16384)             */
+    uint64_t seed;             /* initial weights and sample order            */
+    double lr, beta1, beta2, eps;   /* Adam (1e-3, 0.9, 0.999, 1e-8)          */
+    double init_scale_out;     /* output-layer initial scale (default 0.01)   */
+} stdg_model_config;
+
+typedef struct {
+    int32_t epochs;
+    int64_t samples;           /* elements x steps per epoch                 */
+    double first_loss;         /* mean loss over the first epoch             */
+    double last_loss;          /* mean loss over the last epoch              */
+    double seconds;
+} stdg_train_report;
+
+void stdg_model_config_default(stdg_model_config* cfg);
+
+/* Allocate a model for meshes shaped like `mesh` (device memory: parameters,
+ * Adam moments and batch activations, about 4 * batch * (n_in + 6 hidden)
+ * bytes in FP32).  Weights: seeded uniform Glorot, output layer scaled by
+ * init_scale_out, zero biases.  STDG_ERR_ARG for bad sizes, STDG_ERR_NOMEM. */
+int stdg_model_create(const stdg_mesh* mesh, const stdg_model_config* cfg, stdg_model** out);
+int stdg_model_free(stdg_model* model);
+int stdg_model_info(const stdg_model* model, int64_t* n_params, int32_t* n_in, int32_t* n_out);
+
+/* Host copies of the flat parameters / last gradient (doubles); set_params
+ * also clears the Adam state.  Synchronous. */
+int stdg_model_set_params(stdg_model* model, const double* host);
+int stdg_model_get_params(const stdg_model* model, double* host);
+int stdg_model_get_grads(const stdg_model* model, double* host);
+
+/* Feature rows F [E][n_in] (device doubles) of P, Pm, B (device [E][G][N]).
+ * Asynchronous. */
+int stdg_model_features(stdg_model* model, const stdg_mesh* mesh, const double* P, const double* Pm,
+                        const double* B, double* F, void* stream);
+
+/* Y [n][n_out] = MLP(F [n][n_in]) for 1 <= n <= batch rows (device doubles;
+ * an FP32 model converts).  Asynchronous. */
+int stdg_model_forward(stdg_model* model, const double* F, int64_t n, double* Y, void* stream);
+
+/* Mean squared error of MLP(F) against target [n][n_out] and its gradient
+ * (kept in the model for stdg_model_adam_step / get_grads).  Writes the loss
+ * to *loss (host).  Synchronises the stream. */
+int stdg_model_loss_grad(stdg_model* model, const double* F, const double* target, int64_t n,
+                         double* loss, void* stream);
+
+/* One Adam step (with bias correction) from the stored gradient. */
+int stdg_model_adam_step(stdg_model* model, void* stream);
+
+/* Train on n_steps recorded solves: P, Pm, B, X device [n_steps][E][G][N]
+ * (for step n: p^{n,1}, p^{n-1,1}, the first solve's right-hand side and
+ * p^{n+1,1}; `rec_b`/`rec_x` of stdg_step_opts record the last two).  Each epoch visits every (step, element) sample once in a seeded
+ * random order, in mini-batches.  Synchronises the stream. */
+int stdg_model_train(stdg_model* model, const stdg_mesh* mesh, int32_t n_steps, const double* P,
+                     const double* Pm, const double* B, const double* X, int32_t epochs,
+                     stdg_train_report* report, void* stream);
+
+/* x0 = 2P - Pm + s_D * MLP(features) for every element (device [E][G][N]).
+ * Asynchronous. */
+int stdg_model_predict(stdg_model* model, const stdg_mesh* mesh, const double* P, const double* Pm,
+                       const double* B, double* x0, void* stream);
 
 /* Message of the last error on this thread ("" if none). */
 const char* stdg_last_error(void);

@@ -1,24 +1,25 @@
 """Oracle multilayer perceptron for the learned Krylov initial guess (test infrastructure only).
 
 The pressure-correction solve at the first Picard iteration of a time step
-(Sec. 2.6, step 5 with the zero pressure guess of step 0) has the new
-pressure p^{n+1,1} as its unknown.  A plain Krylov solver starts it from zero
-or from the previous step's pressure p^n.  The learned guess replaces that
-start by
+(Sec. 2.6, step 5 with the zero pressure guess of step 0) yields the first
+Picard pressure p^{n+1,1}.  A plain Krylov solver starts it from zero or from
+the previous step's value P = p^{n,1}.  With Pm = p^{n-1,1}, the learned guess
+corrects the linear extrapolation of that sequence:
 
-    x0 = p^n + s_D * MLP(features),
+    x0 = 2 P - Pm + s_D * MLP(features),
 
 with the network acting element by element on
-    * p^n of the element and of its four face neighbours, divided by s_P,
-    * p^n - p^{n-1} of the same five elements, divided by s_D,
+    * P of the element and of its four face neighbours, divided by s_P,
+    * P - Pm of the same five elements, divided by s_D,
     * the element's own right-hand side b, divided by s_B,
     * four neighbour-present flags,
-where s_P, s_D, s_B are the root-mean-square values of p^n, p^n - p^{n-1}
-and b over the whole mesh (1 when zero).  Slot order: the element itself,
+where s_P, s_D, s_B are the root-mean-square values of P, P - Pm and b over
+the whole mesh (1 when zero).  Slot order: the element itself,
 then the neighbours across local faces 0..3 (local face f is the face
 opposite local vertex f); a missing neighbour (Dirichlet boundary) gives
-zeros and flag 0.  The training target is (x* - p^n) / s_D, x* the solution of
-the solve; the loss is the mean squared error over samples and outputs.
+zeros and flag 0.  The training target is (x* - 2P + Pm) / s_D,
+x* = p^{n+1,1};
+the loss is the mean squared error over samples and outputs.
 
 Network: three affine layers, SiLU after the first two,
     Z1 = F W1 + b1, H1 = silu(Z1), Z2 = H1 W2 + b2, H2 = silu(Z2),
@@ -70,7 +71,8 @@ def flatten(parts):
 def features(P, Pm, B, nbr, elements=None):
     """Feature rows (n, 11 Nst + 4) for the given elements.
 
-    P, Pm, B: (E, Nst) pressure at t^n, at t^{n-1}, right-hand side.
+    P, Pm, B: (E, Nst) the predicted quantity one and two steps back, and the
+    right-hand side.
     nbr: (E, 4) neighbour across local face f, -1 if none.
     """
     P = np.asarray(P, dtype=np.float64)
@@ -92,8 +94,9 @@ def features(P, Pm, B, nbr, elements=None):
 
 
 def target(P, Pm, X):
-    """(x* - p^n) / s_D, shape (E, Nst)."""
-    return (np.asarray(X, dtype=np.float64) - P) / rms(np.asarray(P) - Pm)
+    """(x* - 2P + Pm) / s_D, shape (E, Nst)."""
+    P = np.asarray(P, dtype=np.float64)
+    return (np.asarray(X, dtype=np.float64) - 2.0 * P + Pm) / rms(P - Pm)
 
 
 def forward(theta, F, hidden, n_out):
@@ -135,7 +138,8 @@ def adam_step(theta, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def guess(theta, P, Pm, B, nbr, hidden):
-    """x0 = p^n + s_D * MLP(features), shape (E, Nst)."""
+    """x0 = 2P - Pm + s_D * MLP(features), shape (E, Nst)."""
     F = features(P, Pm, B, nbr)
     Y, _ = forward(theta, F, hidden, P.shape[1])
-    return np.asarray(P, dtype=np.float64) + rms(np.asarray(P) - Pm) * Y
+    P = np.asarray(P, dtype=np.float64)
+    return (2.0 * P - Pm) + rms(P - Pm) * Y

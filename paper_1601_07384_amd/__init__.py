@@ -12,12 +12,16 @@ import numpy as np
 
 from . import _lib
 from ._lib import (Config, MeshInfo, SolveOpts, SolveReport, StepOpts, StepReport, StdgError,
+                   ModelConfig, TrainReport,
                    STDG_OK, STDG_NOT_CONVERGED, STDG_FP64, STDG_FP32,
                    STDG_AUTO, STDG_CG, STDG_GMRES, STDG_CG_TIME, STDG_GUESS_ZERO,
-                   STDG_GUESS_PREVIOUS)
+                   STDG_GUESS_PREVIOUS, STDG_KRYLOV_ZERO, STDG_KRYLOV_PREVIOUS,
+                   STDG_KRYLOV_EXTRAPOLATE, STDG_KRYLOV_LEARNED)
 
-__all__ = ["Mesh", "StdgError", "STDG_FP64", "STDG_FP32", "STDG_AUTO",
+__all__ = ["Mesh", "Model", "StdgError", "STDG_FP64", "STDG_FP32", "STDG_AUTO",
            "STDG_CG", "STDG_GMRES", "STDG_CG_TIME", "STDG_GUESS_ZERO", "STDG_GUESS_PREVIOUS",
+           "STDG_KRYLOV_ZERO", "STDG_KRYLOV_PREVIOUS", "STDG_KRYLOV_EXTRAPOLATE",
+           "STDG_KRYLOV_LEARNED",
            "solve_opts", "step_opts"]
 
 
@@ -42,14 +46,23 @@ def solve_opts(**kw):
     return o
 
 
-def step_opts(n_picard=0, pressure_guess=0, pressure=None, viscous=None):
+def step_opts(n_picard=0, pressure_guess=0, pressure=None, viscous=None, krylov_guess=0,
+              model=None, hist=None, rec_b=None, rec_x=None):
+    """Step options; tensors given here must stay alive until the step returns."""
     o = StepOpts()
     _lib.load().stdg_step_opts_default(ctypes.byref(o))
     o.n_picard = n_picard
     o.pressure_guess = pressure_guess
     for name, kw in (("pressure", pressure), ("viscous", viscous)):
         for k, v in (kw or {}).items():
+            if not hasattr(getattr(o, name), k):
+                raise TypeError(f"unknown {name} option {k}")
             setattr(getattr(o, name), k, v)
+    o.krylov_guess = krylov_guess
+    o.model = model._h.value if model is not None else None
+    for name, t in (("hist", hist), ("rec_b", rec_b), ("rec_x", rec_x)):
+        setattr(o, name, t.data_ptr() if t is not None else None)
+    o._keep = (model, hist, rec_b, rec_x)
     return o
 
 
@@ -145,6 +158,10 @@ class Mesh:
         if g_nodal is not None:
             self._check_any(g_nodal, 3 * self.E * self.Nst)
         o = opts if opts is not None else step_opts(**kw)
+        keep = getattr(o, "_keep", (None, None, None, None))
+        for t, n in zip(keep[1:], (2, 1, 1)):
+            if t is not None:
+                self._check_any(t, n * self.E * self.Nst)
         rep = StepReport()
         g = _ptr(g_nodal) if g_nodal is not None else None
         _lib.check(self._lib.stdg_picard_step(self._h, _ptr(vhat), _ptr(vbar), _ptr(p), g,
@@ -167,6 +184,10 @@ class Mesh:
         self._check_any(div, self.E * self.Nst)
         _lib.check(self._lib.stdg_divergence(self._h, _ptr(vhat), _ptr(div), _stream_ptr(stream)))
 
+    def _check_any_len(self, t):
+        if not t.is_cuda or str(t.dtype) != "torch.float64" or not t.is_contiguous():
+            raise ValueError("expected a contiguous CUDA float64 tensor")
+
     def _check_any(self, t, n):
         if not t.is_cuda or str(t.dtype) != "torch.float64" or not t.is_contiguous():
             raise ValueError("expected a contiguous CUDA float64 tensor")
@@ -178,3 +199,95 @@ class Mesh:
             raise ValueError(f"expected a contiguous CUDA {dtype} tensor")
         if t.numel() != self.E * self.Nst:
             raise ValueError(f"expected {self.E * self.Nst} entries, got {t.numel()}")
+
+
+class Model:
+    """Learned Krylov initial guess (MLP) for meshes shaped like `mesh`.
+
+    Tensors are contiguous CUDA float64 in the library's element order:
+    pressures and right-hand sides [E*G*N] (or [steps*E*G*N] for training),
+    feature rows [n, n_in], outputs [n, n_out].
+    """
+
+    def __init__(self, mesh, hidden=128, precision=STDG_FP32, batch=16384, seed=1601, lr=1e-3,
+                 beta1=0.9, beta2=0.999, eps=1e-8, init_scale_out=0.1):
+        lib = _lib.load()
+        cfg = ModelConfig()
+        lib.stdg_model_config_default(ctypes.byref(cfg))
+        cfg.hidden, cfg.precision, cfg.batch, cfg.seed = hidden, precision, batch, seed
+        cfg.lr, cfg.beta1, cfg.beta2, cfg.eps = lr, beta1, beta2, eps
+        cfg.init_scale_out = init_scale_out
+        h = ctypes.c_void_p()
+        _lib.check(lib.stdg_model_create(mesh._h, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h, self._lib, self.mesh = h, lib, mesh
+        npar, nin, nout = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(lib.stdg_model_info(h, ctypes.byref(npar), ctypes.byref(nin), ctypes.byref(nout)))
+        self.n_params, self.n_in, self.n_out = npar.value, nin.value, nout.value
+        self.hidden, self.batch = hidden, batch
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.stdg_model_free(h)
+            self._h = None
+
+    def params(self):
+        out = np.empty(self.n_params)
+        _lib.check(self._lib.stdg_model_get_params(self._h, out.ctypes.data))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float64)
+        if theta.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        _lib.check(self._lib.stdg_model_set_params(self._h, theta.ctypes.data))
+
+    def grads(self):
+        out = np.empty(self.n_params)
+        _lib.check(self._lib.stdg_model_get_grads(self._h, out.ctypes.data))
+        return out
+
+    def _rows(self, t, width):
+        self.mesh._check_any_len(t)
+        if t.numel() % width:
+            raise ValueError(f"expected rows of {width} values")
+        return t.numel() // width
+
+    def features(self, P, Pm, B, F, stream=None):
+        for t in (P, Pm, B):
+            self.mesh._check_any(t, self.mesh.E * self.mesh.Nst)
+        self.mesh._check_any(F, self.mesh.E * self.n_in)
+        _lib.check(self._lib.stdg_model_features(self._h, self.mesh._h, _ptr(P), _ptr(Pm), _ptr(B),
+                                                 _ptr(F), _stream_ptr(stream)))
+
+    def forward(self, F, Y, stream=None):
+        n = self._rows(F, self.n_in)
+        self.mesh._check_any(Y, n * self.n_out)
+        _lib.check(self._lib.stdg_model_forward(self._h, _ptr(F), n, _ptr(Y), _stream_ptr(stream)))
+
+    def loss_grad(self, F, T, stream=None):
+        n = self._rows(F, self.n_in)
+        self.mesh._check_any(T, n * self.n_out)
+        loss = ctypes.c_double()
+        _lib.check(self._lib.stdg_model_loss_grad(self._h, _ptr(F), _ptr(T), n, ctypes.byref(loss),
+                                                  _stream_ptr(stream)))
+        return loss.value
+
+    def adam_step(self, stream=None):
+        _lib.check(self._lib.stdg_model_adam_step(self._h, _stream_ptr(stream)))
+
+    def train(self, P, Pm, B, X, epochs=1, stream=None):
+        per = self.mesh.E * self.mesh.Nst
+        steps = self._rows(P, per)
+        for t in (Pm, B, X):
+            self.mesh._check_any(t, steps * per)
+        rep = TrainReport()
+        _lib.check(self._lib.stdg_model_train(self._h, self.mesh._h, steps, _ptr(P), _ptr(Pm), _ptr(B),
+                                              _ptr(X), epochs, ctypes.byref(rep), _stream_ptr(stream)))
+        return rep
+
+    def predict(self, P, Pm, B, x0, stream=None):
+        for t in (P, Pm, B, x0):
+            self.mesh._check_any(t, self.mesh.E * self.mesh.Nst)
+        _lib.check(self._lib.stdg_model_predict(self._h, self.mesh._h, _ptr(P), _ptr(Pm), _ptr(B),
+                                                _ptr(x0), _stream_ptr(stream)))

@@ -51,16 +51,24 @@ class SolveOpts(ctypes.Structure):
 class SolveReport(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
                 ("inner_iters", ctypes.c_int32), ("applies", ctypes.c_int32),
-                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("initial_rel_residual", ctypes.c_double)]
 
 
 STDG_GUESS_ZERO = 0
 STDG_GUESS_PREVIOUS = 1
+STDG_KRYLOV_ZERO = 0
+STDG_KRYLOV_PREVIOUS = 1
+STDG_KRYLOV_EXTRAPOLATE = 2
+STDG_KRYLOV_LEARNED = 3
 
 
 class StepOpts(ctypes.Structure):
     _fields_ = [("n_picard", ctypes.c_int32), ("pressure_guess", ctypes.c_int32),
-                ("pressure", SolveOpts), ("viscous", SolveOpts)]
+                ("pressure", SolveOpts), ("viscous", SolveOpts),
+                ("krylov_guess", ctypes.c_int32), ("model", ctypes.c_void_p),
+                ("hist", ctypes.c_void_p), ("rec_b", ctypes.c_void_p),
+                ("rec_x", ctypes.c_void_p)]
 
 
 class StepReport(ctypes.Structure):
@@ -68,7 +76,23 @@ class StepReport(ctypes.Structure):
                 ("max_pressure_residual", ctypes.c_double),
                 ("max_viscous_residual", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("pressure_seconds", ctypes.c_double), ("viscous_seconds", ctypes.c_double),
-                ("pressure_applies", ctypes.c_int32)]
+                ("pressure_applies", ctypes.c_int32), ("first_pressure_iters", ctypes.c_int32),
+                ("first_pressure_seconds", ctypes.c_double),
+                ("first_initial_residual", ctypes.c_double)]
+
+
+class ModelConfig(ctypes.Structure):
+    _fields_ = [("hidden", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("init_scale_out", ctypes.c_double)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("samples", ctypes.c_int64),
+                ("first_loss", ctypes.c_double), ("last_loss", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
 
 
 # (name, restype, argtypes) of every symbol declared in include/stdg.h
@@ -94,6 +118,22 @@ SIGNATURES = [
     ("stdg_dual_from_main", ctypes.c_int, [_P, _P, _P, _P]),
     ("stdg_main_from_dual", ctypes.c_int, [_P, _P, _P, _P]),
     ("stdg_divergence", ctypes.c_int, [_P, _P, _P, _P]),
+    ("stdg_model_config_default", None, [ctypes.POINTER(ModelConfig)]),
+    ("stdg_model_create", ctypes.c_int, [_P, ctypes.POINTER(ModelConfig), ctypes.POINTER(_P)]),
+    ("stdg_model_free", ctypes.c_int, [_P]),
+    ("stdg_model_info", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    ("stdg_model_set_params", ctypes.c_int, [_P, _P]),
+    ("stdg_model_get_params", ctypes.c_int, [_P, _P]),
+    ("stdg_model_get_grads", ctypes.c_int, [_P, _P]),
+    ("stdg_model_features", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    ("stdg_model_forward", ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
+    ("stdg_model_loss_grad", ctypes.c_int, [_P, _P, _P, ctypes.c_int64,
+                                             ctypes.POINTER(ctypes.c_double), _P]),
+    ("stdg_model_adam_step", ctypes.c_int, [_P, _P]),
+    ("stdg_model_train", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32,
+                                         ctypes.POINTER(TrainReport), _P]),
+    ("stdg_model_predict", ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     ("stdg_last_error", ctypes.c_char_p, []),
 ]
 

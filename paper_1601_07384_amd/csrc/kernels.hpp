@@ -20,6 +20,8 @@ hipError_t launch_apply_f32_c(const stdg_mesh* m, const float* C, const float* x
 hipError_t time_mix_f64(const stdg_mesh* m, const double* M, const double* x, double* y, hipStream_t s);
 hipError_t time_mix_f32(const stdg_mesh* m, const float* M, const float* x, float* y, hipStream_t s);
 hipError_t launch_visc_apply(const stdg_mesh* m, const double* x, double* y, hipStream_t s);
+int model_predict(stdg_model* md, const stdg_mesh* m, const double* P, const double* Pm, const double* B,
+                  double* x0, hipStream_t s);
 hipError_t launch_visc_precond(const stdg_mesh* m, const double* x, double* y, hipStream_t s);
 hipError_t convert_d2f(const double* a, float* b, int64_t n, hipStream_t s);
 hipError_t convert_f2d(const float* a, double* b, int64_t n, hipStream_t s);

@@ -677,7 +677,7 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
     if (!std::isfinite(bn2)) { set_error("non-finite right-hand side"); return STDG_ERR_NUMERIC; }
     const double bnorm = std::sqrt(bn2);
     int status = STDG_OK, inner_total = 0, outer = 0;
-    double rel = 0.0;
+    double rel = 0.0, rel0 = 0.0;
     // shift x to x_anchor = 0, set q = S x, r = b~ - S x (consistent residual)
     // and return the anchored relative residual ||b_a - S_a x|| / ||b_a||.
     auto check = [&](double& out) -> int {
@@ -701,10 +701,12 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
         int it = 0;
         double res = 0.0, tol_abs = o.rtol * bnorm;
         outer = 1;
+        if (int e = check(rel0)) return e;
+        rel = rel0;
         // the recursive residual may drift from the true one: restart from the
         // true residual (with a tighter target) until the anchored residual
         // meets the tolerance
-        for (int round = 0; round < 6; ++round) {
+        for (int round = 0; round < 6 && rel > o.rtol; ++round) {
             const int left = o.max_iter - inner_total;
             if (left <= 0) { status = STDG_NOT_CONVERGED; break; }
             status = run_krylov<double>(c, o.method, w.z, x, w.r, w.p, w.q, w.V, mres, tol_abs, left,
@@ -720,6 +722,7 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
         // FP64 iterative refinement around FP32 Krylov solves
         for (outer = 1; outer <= o.max_outer + 1; ++outer) {
             if (int e = check(rel)) return e;
+            if (outer == 1) rel0 = rel;
             if (rel <= o.rtol) { status = STDG_OK; break; }
             if (outer > o.max_outer || inner_total >= o.max_iter) { status = STDG_NOT_CONVERGED; break; }
             // inner right-hand side: the consistent residual projected on the
@@ -734,8 +737,12 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
             if (int e = read_scal(c, S_NORM, rn)) return e;
             int it = 0;
             double res = 0.0;
+            // each inner solve reduces the residual by inner_rtol, but never
+            // further than the final tolerance needs (a good initial guess
+            // then saves inner iterations instead of overshooting)
+            const double inner_abs = std::max(o.inner_rtol * rn, 0.25 * o.rtol * bnorm);
             status = run_krylov<float>(c, o.method, w.b32, w.x32, w.r32, w.p32, w.q32, w.V32, mres,
-                                       o.inner_rtol * rn, o.max_iter - inner_total, o.check_every, it, res);
+                                       inner_abs, o.max_iter - inner_total, o.check_every, it, res);
             inner_total += it;
             if (status < 0) return status;
             hipLaunchKernelGGL(k_add_f32, dim3(gb), dim3(256), 0, c.s, x, w.x32, n);
@@ -750,6 +757,7 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
         rep->inner_iters = inner_total;
         rep->applies = c.applies;
         rep->rel_residual = rel;
+        rep->initial_rel_residual = rel0;
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;

@@ -577,6 +577,11 @@ extern "C" void stdg_step_opts_default(stdg_step_opts* o) {
     stdg_solve_opts_default(&o->pressure);
     stdg_solve_opts_default(&o->viscous);
     o->viscous.rtol = 1e-12;
+    o->krylov_guess = STDG_KRYLOV_ZERO;
+    o->model = nullptr;
+    o->hist = nullptr;
+    o->rec_b = nullptr;
+    o->rec_x = nullptr;
 }
 
 extern "C" int stdg_dual_from_main(const stdg_mesh* m, const double* vbar, double* vhat, void* stream) {
@@ -624,6 +629,14 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         set_error("unknown pressure guess");
         return STDG_ERR_ARG;
     }
+    const int kg = opts->krylov_guess;
+    if (kg != STDG_KRYLOV_ZERO && kg != STDG_KRYLOV_PREVIOUS && kg != STDG_KRYLOV_EXTRAPOLATE &&
+        kg != STDG_KRYLOV_LEARNED) {
+        set_error("unknown Krylov guess");
+        return STDG_ERR_ARG;
+    }
+    if (kg != STDG_KRYLOV_ZERO && !opts->hist) { set_error("this Krylov guess needs hist"); return STDG_ERR_ARG; }
+    if (kg == STDG_KRYLOV_LEARNED && !opts->model) { set_error("the learned guess needs a model"); return STDG_ERR_ARG; }
     hipStream_t s = (hipStream_t)stream;
     const int G = m->G, N = m->N;
     const int64_t nD = 3 * F * G * N, nM = 3 * E * G * N, nP = E * G * N;
@@ -651,6 +664,8 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     double* bp = pk + nP;
     double* dp = bp + nP;
     double* kw = dp + nP;           // viscous Krylov work
+    double* h0 = opts->hist;        // first-iteration pressures of the two previous steps
+    double* h1 = opts->hist ? opts->hist + nP : nullptr;
     const double dt = m->cfg.dt;
     // step 0
     hipLaunchKernelGGL(k_copyd, dim3(nblk(nM)), dim3(256), 0, s, vbar, vprev, nM);
@@ -671,8 +686,8 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     else
         hipLaunchKernelGGL(k_zero, dim3(nblk(nP)), dim3(256), 0, s, pk, nP);
     STDG_HIP(hipGetLastError());
-    int piters = 0, viters = 0, papplies = 0;
-    double pres = 0.0, vres = 0.0, psec = 0.0, vsec = 0.0;
+    int piters = 0, viters = 0, papplies = 0, first_iters = 0;
+    double pres = 0.0, vres = 0.0, psec = 0.0, vsec = 0.0, first_sec = 0.0, first_res0 = 0.0;
     for (int k = 0; k < npic; ++k) {
         // step 1
         if (int e = stdg_main_from_dual(m, vk, vbk, s)) return e;
@@ -706,21 +721,54 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         // step 5
         hipLaunchKernelGGL(k_rhs_pressure, dim3(nblk(nP)), dim3(256), 0, s, d.QT, m->d.cls, d.tet_face, d.W, Fv, dt,
                            bp, E, F, G, N);
-        hipLaunchKernelGGL(k_zero, dim3(nblk(nP)), dim3(256), 0, s, dp, nP);
+        STDG_HIP(hipStreamSynchronize(s));
+        const auto tg0 = std::chrono::steady_clock::now();
+        if (k == 0 && opts->rec_b)
+            hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, bp, opts->rec_b, nP);
+        // guesses x0 are for the new pressure p^{n+1,1}; the unknown is its
+        // correction to p^{n+1,0}
+        if (k == 0 && kg == STDG_KRYLOV_LEARNED) {
+            if (int e2 = model_predict(opts->model, m, h0, h1, bp, dp, s)) return e2;
+            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, pk, -1.0, nP);
+        } else if (k == 0 && kg == STDG_KRYLOV_PREVIOUS) {
+            hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, h0, dp, nP);
+            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, pk, -1.0, nP);
+        } else if (k == 0 && kg == STDG_KRYLOV_EXTRAPOLATE) {
+            hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, h0, dp, nP);
+            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, h0, 1.0, nP);
+            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, h1, -1.0, nP);
+            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, pk, -1.0, nP);
+        } else {
+            hipLaunchKernelGGL(k_zero, dim3(nblk(nP)), dim3(256), 0, s, dp, nP);
+        }
         STDG_HIP(hipGetLastError());
         stdg_solve_report prep;
         STDG_HIP(hipStreamSynchronize(s));
+        const double guess_sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - tg0).count();
         e = stdg_pressure_solve(m, bp, dp, &opts->pressure, &prep, s);
         if (e < 0) return e;
         piters += prep.inner_iters;
         papplies += prep.applies;
-        psec += prep.seconds;
+        psec += prep.seconds + guess_sec;
         pres = std::max(pres, prep.rel_residual);
+        if (k == 0) {
+            first_iters = prep.inner_iters;
+            first_sec = prep.seconds + guess_sec;
+            first_res0 = prep.initial_rel_residual;
+        }
         // step 6
         hipLaunchKernelGGL(k_dualgrad, dim3(nblk(nD)), dim3(256), 0, s, d.US, d.UN, m->d.cls, d.fl, d.flf, d.fr, d.TW,
                            dp, dt, wg, F, G, N);
         hipLaunchKernelGGL(k_update, dim3(nblk(nD)), dim3(256), 0, s, Fv, wg, vk, F, NI, G, N);
         hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, pk, dp, 1.0, nP);
+        if (k == 0) {
+            // pk = p^{n+1,1}: record it and push it into the history
+            if (opts->rec_x) hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, pk, opts->rec_x, nP);
+            if (h0) {
+                hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, h0, h1, nP);
+                hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, pk, h0, nP);
+            }
+        }
         STDG_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_copyd, dim3(nblk(nD)), dim3(256), 0, s, vk, vhat, nD);
@@ -736,6 +784,9 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         rep->pressure_seconds = psec;
         rep->viscous_seconds = vsec;
         rep->pressure_applies = papplies;
+        rep->first_pressure_iters = first_iters;
+        rep->first_pressure_seconds = first_sec;
+        rep->first_initial_residual = first_res0;
     }
     return STDG_OK;
 }

@@ -136,14 +136,17 @@ def test_feature_gather_against_brute_force_adjacency():
     assert (nbr < 0).any()
 
 
-def test_zero_network_guess_is_previous_pressure():
+def test_zero_network_guess_is_linear_extrapolation():
     X, T = kuhn_mesh(2)
     E, nst, hidden = T.shape[0], 4, 6
     nbr = _brute_neighbours(T)
     rng = np.random.default_rng(6)
     P, Pm, B = (rng.standard_normal((E, nst)) for _ in range(3))
     theta = np.zeros(sum(int(np.prod(s)) for s in mlp.shapes(mlp.n_inputs(nst), hidden, nst)))
-    assert np.array_equal(mlp.guess(theta, P, Pm, B, nbr, hidden), P)
+    assert np.array_equal(mlp.guess(theta, P, Pm, B, nbr, hidden), 2.0 * P - Pm)
+    # a sequence linear in the step index (Pm, P, 2P - Pm) needs no correction
+    X2 = 2.0 * P - Pm
+    assert np.abs(mlp.target(P, Pm, X2)).max() <= 1e-14 * np.abs(X2).max()
 
 
 def test_adam_reduces_loss_on_a_linear_target():
