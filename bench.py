@@ -15,8 +15,13 @@ the plain-vs-chosen pressure-solve comparison.
 
 `value` is the whole-job Schur-operator throughput: pressure-operator
 applications in the timed steps x DoF / timed wall time (GDoF/s).  The
-roofline entry is for the Schur-apply kernel, timed with HIP events over a
-burst of launches on the library's stream right after the timed steps.
+roofline entry is for the step's dominant kernel, the fused FP32 CG operator
+kernel (p = r + beta p, q = (B (x) I) p on MFMA, partial p.q), timed with HIP
+events on the library's stream over a burst of launches through
+stdg_pressure_apply_spatial_f32 (the same kernel with beta = 0) right after
+the timed steps.  Algorithmic bytes per launch: read r and p, write p and q
+once (4 x 4 B per DoF) plus 20 B of indices per element; flops: 2 N^2 x 5
+blocks per column.  The FP64 Schur apply is timed the same way (context).
 """
 
 import argparse
@@ -32,6 +37,7 @@ import numpy as np  # noqa: E402
 
 N_HEX, P_DEG, P_GAMMA, DT, NU = 24, 3, 1, 1e-3, 1e-3
 FP64_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
@@ -124,9 +130,25 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     t_apply = ev0.elapsed_time(ev1) / 1e3 / args.applies
+    # ---- the fused FP32 CG operator kernel (same kernel, beta = 0) in a burst
+    xf = torch.randn(E * Nst, dtype=torch.float32, device=dev)
+    yf = torch.empty_like(xf)
+    for _ in range(10):
+        m.apply_spatial_f32(xf, yf)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.applies):
+        m.apply_spatial_f32(xf, yf)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    k_us = ev0.elapsed_time(ev1) * 1e3 / args.applies
     dofs = E * Nst
     flops = 2.0 * N * N * G * 5 * E + 2.0 * N * G * G * E          # 5 N x N blocks x G columns + time mix
     bytes_alg = 2.0 * dofs * 8 + 20.0 * E                           # x and y once, 5 int32 indices
+    # fused FP32 CG operator kernel (B (x) I): r, p read, p, q written once
+    k_bytes = 4.0 * dofs * 4 + 20.0 * E
+    k_flops = 2.0 * N * N * 5 * E * G
+    k_s = k_us * 1e-6 if k_us > 0 else float("nan")
 
     # ---- plain form from the state before the timed steps
     plain_rep = None
@@ -149,7 +171,7 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": t_steps / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": "periodic unit cube, 24^3 hexahedra x 6 = 82,944 tets, p=3, "
                                "p_gamma=1 (40 DoF/tet), nu=1e-3, dt=1e-3, 2 Picard iterations "
                                "per step, 16 seeded Fourier modes",
@@ -165,11 +187,16 @@ def main():
             "plain_form": "FP64 GMRES(50) on the space-time system",
             "plain_iters": plain_rep.pressure_iters if plain_rep else None,
             "chosen_vs_plain_rel_diff": {"vhat": err_v, "p": err_p} if plain_rep else None},
-        "apply_kernel": {"us": t_apply * 1e6, "gdofs": dofs / t_apply / 1e9},
-        "roofline": {"bound": "alu", "achieved": flops / t_apply / 1e12, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": flops / t_apply / 1e12 / FP64_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "schur_apply_lds<20,2,double>",
-                     "hbm_gbs_algorithmic": bytes_alg / t_apply / 1e9},
+        "fp64_apply_kernel": {"kernel": "schur_apply_lds<20,2,double>", "us": t_apply * 1e6,
+                              "gdofs": dofs / t_apply / 1e9, "tflops": flops / t_apply / 1e12,
+                              "frac_fp64_peak": flops / t_apply / 1e12 / FP64_PEAK_TFLOPS,
+                              "hbm_gbs_algorithmic": bytes_alg / t_apply / 1e9},
+        "roofline": {"bound": "hbm", "achieved": k_bytes / k_s / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": k_bytes / k_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_cg_spmv<{N}>", "kernel_us": k_us, "kernel_launches": args.applies,
+                     "bytes_per_launch": k_bytes, "flops_per_launch": k_flops,
+                     "mfma_tflops": k_flops / k_s / 1e12,
+                     "mfma_frac_fp32": k_flops / k_s / 1e12 / FP32_MFMA_PEAK_TFLOPS},
         "mesh_build_s": build_s,
     }
     if not args.no_cpu_baseline:

@@ -170,6 +170,13 @@ typedef struct {
     double initial_rel_residual;  /* the same for the initial guess            */
 } stdg_solve_report;
 
+/* y = (B (x) I) x in FP32: the spatial Schur operator B = dt^2 S^sp of
+ * eq. CS_19 (F3 factorisation S = B (x) C) on every time node, i.e. the
+ * operator of the time-decoupled solve (STDG_CG_TIME).  x, y: device
+ * [E][G][N] floats, 16-byte aligned.  Runs the FP32 MFMA kernel of the fused
+ * CG iteration (p = 1, 2, 3).  Asynchronous; uses the mesh's workspace. */
+int stdg_pressure_apply_spatial_f32(const stdg_mesh* mesh, const float* x, float* y, void* stream);
+
 /* Fill opts with defaults: AUTO, restart 50, rtol 1e-10, max_iter 20000,
  * FP64, inner_rtol 1e-4, max_outer 30, check_every 8. */
 void stdg_solve_opts_default(stdg_solve_opts* opts);

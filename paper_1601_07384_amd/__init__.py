@@ -139,6 +139,12 @@ class Mesh:
         _lib.check(self._lib.stdg_pressure_apply_f32(self._h, _ptr(x), _ptr(y),
                                                      _stream_ptr(stream)))
 
+    def apply_spatial_f32(self, x, y, stream=None):
+        """y = (B (x) I) x: the spatial operator on every time node, FP32."""
+        self._check_vec(x, "float32"); self._check_vec(y, "float32")
+        _lib.check(self._lib.stdg_pressure_apply_spatial_f32(self._h, _ptr(x), _ptr(y),
+                                                             _stream_ptr(stream)))
+
     def solve(self, b, x, opts=None, stream=None, **kw):
         """Anchored pressure solve; x holds the guess on entry.  Returns the report."""
         self._check_vec(b, "float64"); self._check_vec(x, "float64")

@@ -109,6 +109,7 @@ SIGNATURES = [
     ("stdg_mesh_free", None, [_P]),
     ("stdg_pressure_apply", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     ("stdg_pressure_apply_f32", ctypes.c_int, [_P, _P, _P, _P]),
+    ("stdg_pressure_apply_spatial_f32", ctypes.c_int, [_P, _P, _P, _P]),
     ("stdg_solve_opts_default", None, [ctypes.POINTER(SolveOpts)]),
     ("stdg_pressure_solve", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(SolveOpts),
                                             ctypes.POINTER(SolveReport), _P]),

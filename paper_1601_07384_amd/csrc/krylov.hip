@@ -23,6 +23,8 @@
 #include <cmath>
 #include <vector>
 
+#include <type_traits>
+
 #include "internal.hpp"
 #include "kernels.hpp"
 
@@ -35,6 +37,8 @@ constexpr int NBLK = 1024;  // reduction blocks (fixed: determinism)
 
 enum Slot {
     S_RR = 0, S_PQ, S_ALPHA, S_BETA, S_RES, S_BN2, S_RN2, S_NORM, S_INV, S_TMP,
+    S_FRR = 10,         // fused CG: rr of even / odd iterations (two slots)
+    S_CHK = 12,         // fused CG: lagged residual checks (two slots)
     S_TIME = 16,        // G per-time-node sums
     S_ANCH = 32,        // G anchor values
     S_COUNT = 64
@@ -382,11 +386,91 @@ int time_sums(Ctx& c, const double* v) {
     return STDG_OK;
 }
 
+// FP32 CG with the fused two-kernel iteration (operator B (x) I only).
+bool cg_fusable(const Ctx& c) {
+    const stdg_mesh* m = c.m;
+    static_assert(CG_UPD_BLOCKS == NBLK, "the update kernel's partials share the residual layout");
+    return (c.op == 2 || (c.op == 0 && m->G == 1)) && cg_fused_supported(m) && m->ws.p32b &&
+           NBLK + cg_spmv_blocks(m) <= (int64_t)NBLK * 208;
+}
+
+int cg_fused(Ctx& c, const float* b, float* x, float* r, float* p, float* q, double tol_abs, int max_it,
+             int check_every, int& iters, double& res_out) {
+    const stdg_mesh* m = c.m;
+    const int64_t n = c.n;
+    const int gb = grid_for(n);
+    float* pa = p;
+    float* pb = m->ws.p32b;
+    const float cscale = c.op == 2 ? 1.0f : (float)m->Ctime[0];
+    double* upart = c.partial;                   // NBLK partials of r.r
+    double* spart = c.partial + NBLK;            // operator-kernel partials of p.q
+    const int64_t nsp = cg_spmv_blocks(m);
+    CK(Apply<float>::run(c, x, q)); c.applies++;
+    hipLaunchKernelGGL((k_resid<float, float>), dim3(NBLK), dim3(RT), 0, c.s, b, q, r, n, upart);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, upart, NBLK, c.scal, (int)S_TMP, (int)FIN_STORE);
+    hipLaunchKernelGGL(k_fill<float>, dim3(gb), dim3(256), 0, c.s, pa, 0.0f, n);
+    CK(hipGetLastError());
+    double rr;
+    if (int e = read_scal(c, S_TMP, rr)) return e;
+    iters = 0;
+    res_out = std::sqrt(rr);
+    if (res_out <= tol_abs) return STDG_OK;
+    // Residual checks lag one polling interval: the check enqueued after
+    // iteration i is read once iteration i + check_every has been enqueued,
+    // so the device queue never drains while the host waits.  A solve thus
+    // runs up to check_every iterations past the one that met the tolerance.
+    hipEvent_t const* ev = m->ws.ev;
+    int slot = 0, pending = -1;
+    auto enqueue_check = [&](int sl) -> int {
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, upart, NBLK, c.scal, (int)S_CHK + sl,
+                           (int)FIN_STORE);
+        CK(hipMemcpyAsync(c.hscal + 2 + sl, c.scal + S_CHK + sl, sizeof(double), hipMemcpyDeviceToHost, c.s));
+        CK(hipEventRecord(ev[sl], c.s));
+        return STDG_OK;
+    };
+    auto read_check = [&](int sl, double& v) -> int {
+        CK(hipEventSynchronize(ev[sl]));
+        v = c.hscal[2 + sl];
+        if (!std::isfinite(v)) { set_error("non-finite residual in CG"); return STDG_ERR_NUMERIC; }
+        return STDG_OK;
+    };
+    while (iters < max_it) {
+        CK(launch_cg_spmv_f32(m, r, pa, pb, q, c.scal, S_FRR, iters, cscale, upart, NBLK, spart, c.s));
+        c.applies++;
+        CK(launch_cg_upd_f32(x, r, pb, q, c.scal, S_FRR, iters, n, spart, nsp, upart, c.s));
+        std::swap(pa, pb);
+        ++iters;
+        if (iters % check_every == 0 || iters == max_it) {
+            if (int e = enqueue_check(slot)) return e;
+            if (pending >= 0) {
+                if (int e = read_check(slot ^ 1, rr)) return e;
+                if (std::sqrt(rr) <= tol_abs) {
+                    // converged at the previous check; report the newest residual
+                    if (int e = read_check(slot, rr)) return e;
+                    res_out = std::sqrt(rr);
+                    return STDG_OK;
+                }
+            }
+            pending = iters;
+            slot ^= 1;
+        }
+    }
+    if (pending >= 0) {
+        if (int e = read_check(slot ^ 1, rr)) return e;
+        res_out = std::sqrt(rr);
+        if (res_out <= tol_abs) return STDG_OK;
+    }
+    return STDG_NOT_CONVERGED;
+}
+
 // CG on S x = b (consistent); x, b, work vectors of type T.  Stops when the
 // recursive residual norm <= tol_abs or after max_it iterations.
 template <typename T>
 int cg(Ctx& c, const T* b, T* x, T* r, T* p, T* q, double tol_abs, int max_it, int check_every,
        int& iters, double& res_out) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (cg_fusable(c)) return cg_fused(c, b, x, r, p, q, tol_abs, max_it, check_every, iters, res_out);
+    }
     const int64_t n = c.n;
     const int gb = grid_for(n);
     CK(Apply<T>::run(c, x, q)); c.applies++;
@@ -513,8 +597,12 @@ int ensure_workspace(stdg_mesh* m, int mres, bool need32) {
         STDG_HIP(hipHostMalloc(&w.hscal, sizeof(double) * 8));
     }
     if (need32) {
-        for (float** f : {&w.r32, &w.p32, &w.q32, &w.x32, &w.b32})
+        for (float** f : {&w.r32, &w.p32, &w.q32, &w.x32, &w.b32, &w.p32b})
             if (!*f) STDG_HIP(hipMalloc(f, n * sizeof(float)));
+        if (!w.ev[0]) {
+            STDG_HIP(hipEventCreate(&w.ev[0]));
+            STDG_HIP(hipEventCreate(&w.ev[1]));
+        }
     }
     if (mres > w.restart) {
         if (w.V) STDG_HIP(hipFree(w.V));
@@ -532,9 +620,12 @@ int ensure_workspace(stdg_mesh* m, int mres, bool need32) {
 void free_workspace(stdg_mesh* m) {
     Workspace& w = m->ws;
     for (void* p : {(void*)w.r, (void*)w.p, (void*)w.q, (void*)w.z, (void*)w.V, (void*)w.r32, (void*)w.p32,
-                    (void*)w.q32, (void*)w.x32, (void*)w.b32, (void*)w.V32, (void*)w.partial, (void*)w.scal})
+                    (void*)w.q32, (void*)w.x32, (void*)w.b32, (void*)w.V32, (void*)w.partial, (void*)w.scal,
+                    (void*)w.p32b})
         if (p) (void)hipFree(p);
     if (w.hscal) (void)hipHostFree(w.hscal);
+    for (hipEvent_t e : w.ev)
+        if (e) (void)hipEventDestroy(e);
     w = Workspace();
 }
 
@@ -761,4 +852,19 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;
+}
+
+// y = (B (x) I) x in FP32 with the fused CG operator kernel (beta = 0).
+extern "C" int stdg_pressure_apply_spatial_f32(const stdg_mesh* cm, const float* x, float* y, void* stream) {
+    if (!cm || !x || !y) { set_error("null argument"); return STDG_ERR_ARG; }
+    stdg_mesh* m = const_cast<stdg_mesh*>(cm);
+    if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
+    if (!cg_fused_supported(m)) { set_error("the FP32 spatial operator kernel supports p = 1, 2, 3"); return STDG_ERR_ARG; }
+    if (int e = ensure_workspace(m, 0, true)) return e;
+    Workspace& w = m->ws;
+    if (NBLK + cg_spmv_blocks(m) > (int64_t)NBLK * 208) { set_error("mesh too large for the reduction buffer"); return STDG_ERR_ARG; }
+    const hipError_t e = launch_cg_spmv_f32(m, x, x, w.p32b, y, w.scal, S_FRR, 0, 1.0f, w.partial, NBLK,
+                                           w.partial + NBLK, (hipStream_t)stream);
+    if (e != hipSuccess) { set_error(std::string("spatial apply: ") + hipGetErrorString(e)); return STDG_ERR_DEVICE; }
+    return STDG_OK;
 }

@@ -202,3 +202,62 @@ def test_solve_reports_not_converged_and_nan():
     with pytest.raises(P.StdgError) as e:
         m.solve(b, x)
     assert e.value.code == -3
+
+
+@pytest.mark.parametrize("n,p,pg,periodic,method", [(4, 3, 1, True, P.STDG_CG_TIME),
+                                                    (4, 1, 2, False, P.STDG_CG_TIME),
+                                                    (5, 2, 0, False, P.STDG_CG)])
+def test_fp32_solve_deterministic_and_accurate(n, p, pg, periodic, method):
+    """The FP32 inner CG (fused iteration with last-block reductions) gives
+    bitwise-identical results on repeated calls, and the refined solution
+    meets the FP64 residual; Dirichlet meshes exercise mixed-class chunks."""
+    print(f"fp32 determinism n={n} p={p} pg={pg} periodic={periodic}", flush=True)
+    X, T = case_mesh(n)
+    m = P.Mesh(X, T, p, pg, dt=1e-2, periodic=periodic)
+    b = gpu(np.random.default_rng(21).standard_normal(m.E * m.Nst))
+    xs, reps = [], []
+    for _ in range(2):
+        x = torch.zeros_like(b)
+        reps.append(m.solve(b, x, method=method, precision=P.STDG_FP32, rtol=1e-11))
+        torch.cuda.synchronize()
+        xs.append(x.cpu().numpy())
+    assert reps[0].status == 0 and reps[0].rel_residual <= 1e-11
+    assert reps[0].inner_iters == reps[1].inner_iters
+    assert np.array_equal(xs[0], xs[1])
+    x64 = torch.zeros_like(b)
+    m.solve(b, x64, method=method if method != P.STDG_CG_TIME else P.STDG_GMRES, rtol=1e-12, restart=60)
+    ref = x64.cpu().numpy()
+    assert np.abs(xs[0] - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+SQ3 = np.sqrt(3.0)
+
+
+@pytest.mark.parametrize("n,p,pg,periodic", [(4, 3, 1, True), (3, 2, 0, False), (3, 1, 1, False),
+                                             (5, 3, 0, False)])
+def test_spatial_apply_f32_matches_oracle(n, p, pg, periodic):
+    """(B (x) I) x = S (I (x) C^-1) x, with C = W T^-1 W from the hand-derived
+    time matrices (W = I/2 and T of the p_gamma = 1 Gauss-Legendre basis; C = 1
+    for p_gamma = 0).  FP32 MFMA kernel against the FP64 oracle, 1e-5
+    relative; Dirichlet meshes give tiles that mix geometry classes."""
+    print(f"spatial f32 n={n} p={p} pg={pg} periodic={periodic}", flush=True)
+    X, T = case_mesh(n)
+    m = P.Mesh(X, T, p, pg, dt=0.05, periodic=periodic)
+    ops = SpaceTimeOperators(OracleMesh(X, T, periodic=periodic), p, pg, 0.05)
+    if pg == 0:
+        Cinv = np.eye(1)
+    else:
+        Tc = np.array([[1.0, (SQ3 - 1) / 2], [-(SQ3 + 1) / 2, 1.0]])
+        W = 0.5 * np.eye(2)
+        Cinv = np.linalg.inv(W @ np.linalg.inv(Tc) @ W)
+    G, N = m.G, m.N
+    x = np.random.default_rng(31).standard_normal((m.E, G, N)).astype(np.float32).astype(np.float64)
+    xs = np.einsum("ab,ebn->ean", Cinv, x)
+    perm = m.permutation()
+    yo = apply_S(ops, to_input(xs.reshape(m.E, m.Nst), perm))
+    xf = gpu(x.ravel(), torch.float32)
+    yf = torch.empty_like(xf)
+    m.apply_spatial_f32(xf, yf)
+    torch.cuda.synchronize()
+    yg = to_input(yf.cpu().numpy().astype(np.float64).reshape(m.E, m.Nst), perm)
+    assert np.abs(yg - yo).max() <= 1e-5 * np.abs(yo).max()
