@@ -109,6 +109,7 @@ static int mesh_build_impl(const double* xyz, int64_t n_vert, const int64_t* tet
             e = build_topology(m, xyz, n_vert, tets, &order);
             if (e == STDG_OK) e = assign_classes(m, rep);
         }
+        if (e == STDG_OK) sort_faces_by_class(m);
         if (e == STDG_OK) e = build_blocks(m, rep);
         if (e == STDG_OK) e = build_picard_tables(m, rep);
         if (e == STDG_OK) {

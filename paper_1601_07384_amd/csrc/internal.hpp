@@ -77,7 +77,8 @@ struct PicardTables {
 struct PicardDevice {
     double *A = nullptr, *GB = nullptr, *QT = nullptr, *US = nullptr, *UN = nullptr, *BB = nullptr;
     double *SVT = nullptr, *MIT = nullptr, *DV = nullptr;
-    double *SVt = nullptr, *MIt = nullptr;   // blocks transposed (column-major) for the fast kernel
+    double *SVt = nullptr, *MIt = nullptr;   // blocks transposed (column-major) for the register kernels
+    double *At = nullptr, *GBt = nullptr, *QTt = nullptr, *USt = nullptr, *UNt = nullptr, *BBt = nullptr;
     double *cJinv = nullptr, *cdet = nullptr, *cnrm = nullptr, *PHf = nullptr, *PHn = nullptr, *FW = nullptr;
     double *PHv = nullptr, *dPHv = nullptr, *wv = nullptr, *tq = nullptr, *tw = nullptr, *gq = nullptr;
     double *Tm = nullptr, *TW = nullptr, *W = nullptr, *g0g1 = nullptr, *g1 = nullptr;

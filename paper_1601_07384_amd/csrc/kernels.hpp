@@ -31,6 +31,15 @@ hipError_t time_mix_f32(const stdg_mesh* m, const float* M, const float* x, floa
 hipError_t launch_visc_apply(const stdg_mesh* m, const double* x, double* y, hipStream_t s);
 int model_predict(stdg_model* md, const stdg_mesh* m, const double* P, const double* Pm, const double* B,
                   double* x0, hipStream_t s);
+bool fast_rows_supported(const stdg_mesh* m);
+hipError_t fast_dualgrad(const stdg_mesh* m, const double* p, double dt, double* w, hipStream_t s);
+hipError_t fast_goback(const stdg_mesh* m, const double* vbar, const double* vbdry, double* out, int64_t f0,
+                       int64_t f1, hipStream_t s);
+hipError_t fast_average(const stdg_mesh* m, const double* vhat, double* vbar, hipStream_t s);
+hipError_t fast_rhs_pressure(const stdg_mesh* m, const double* Fv, double dt, double* b, hipStream_t s);
+hipError_t fast_visc_rhs(const stdg_mesh* m, const double* vprev, const double* ups, const double* lam,
+                         const double* vbc, double* rhs, hipStream_t s);
+hipError_t fast_blockdiag(const stdg_mesh* m, const double* x, double* y, hipStream_t s);
 hipError_t launch_visc_precond(const stdg_mesh* m, const double* x, double* y, hipStream_t s);
 hipError_t convert_d2f(const double* a, float* b, int64_t n, hipStream_t s);
 hipError_t convert_f2d(const float* a, double* b, int64_t n, hipStream_t s);
@@ -39,6 +48,7 @@ int build_topology(stdg_mesh* m, const double* xyz, int64_t n_vert, const int64_
                    const std::vector<int64_t>* order);
 int assign_classes(stdg_mesh* m, std::vector<int64_t>& rep);
 std::vector<int64_t> class_chunk_order(const stdg_mesh* m);
+void sort_faces_by_class(stdg_mesh* m);
 int build_blocks(stdg_mesh* m, const std::vector<int64_t>& rep);
 int upload_tables(stdg_mesh* m);
 void free_tables(stdg_mesh* m);

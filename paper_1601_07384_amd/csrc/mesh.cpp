@@ -14,6 +14,7 @@
 #include <omp.h>
 
 #include <algorithm>
+#include <tuple>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -407,6 +408,27 @@ int assign_classes(stdg_mesh* m, std::vector<int64_t>& rep) {
 // the classes, so that every full wavefront holds a single class and the
 // chunks of all classes advance through space together; the partial
 // remainder of each class goes to the end so full chunks stay aligned.
+// Order faces by the classes and local faces of their two elements (interior
+// faces first, then boundary faces), then by the left element.  Face
+// operators are stored per (class of the left element, its local face), so
+// consecutive faces share operator blocks and a wavefront of face threads
+// usually reads one block set.
+void sort_faces_by_class(stdg_mesh* m) {
+    auto key = [&](const Face& F) {
+        const int64_t cl = m->cls[F.left], cr = F.right >= 0 ? m->cls[F.right] : -1;
+        return std::make_tuple(cl, F.lf, cr, F.rf, F.left);
+    };
+    const int64_t NI = m->n_interior;
+    std::sort(m->faces.begin(), m->faces.begin() + NI,
+              [&](const Face& a, const Face& b) { return key(a) < key(b); });
+    std::sort(m->faces.begin() + NI, m->faces.end(), [&](const Face& a, const Face& b) { return key(a) < key(b); });
+    for (int64_t j = 0; j < (int64_t)m->faces.size(); ++j) {
+        const Face& F = m->faces[j];
+        m->tet_face[4 * F.left + F.lf] = j;
+        if (F.right >= 0) m->tet_face[4 * F.right + F.rf] = j;
+    }
+}
+
 std::vector<int64_t> class_chunk_order(const stdg_mesh* m) {
     const int W = 64;
     std::vector<std::vector<int64_t>> lists(m->n_classes);

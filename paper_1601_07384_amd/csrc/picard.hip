@@ -487,6 +487,53 @@ int upload(T*& dst, const std::vector<T>& src) {
 
 }  // namespace
 
+// Block-row steps: the register kernels of picard_fast.hip for p <= 4, the
+// thread-per-coefficient kernels above otherwise.
+hipError_t run_goback(const stdg_mesh* m, const double* vbar, const double* vbdry, double* out, int64_t f0,
+                      int64_t f1, hipStream_t s) {
+    if (fast_rows_supported(m)) return fast_goback(m, vbar, vbdry, out, f0, f1, s);
+    const PicardDevice& d = m->pd;
+    const int64_t n = 3 * (f1 - f0) * m->G * m->N;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_goback, dim3(nblk(n)), dim3(256), 0, s, d.GB, m->d.cls, d.fl, d.flf, d.fr, d.frf, vbar, vbdry,
+                       out, f0, f1, (int64_t)m->faces.size(), m->E, m->G, m->N);
+    return hipGetLastError();
+}
+
+hipError_t run_average(const stdg_mesh* m, const double* vhat, double* vbar, hipStream_t s) {
+    if (fast_rows_supported(m)) return fast_average(m, vhat, vbar, s);
+    const int64_t n = 3 * m->E * m->Nst;
+    hipLaunchKernelGGL(k_average, dim3(nblk(n)), dim3(256), 0, s, m->pd.A, m->d.cls, m->pd.tet_face, vhat, vbar, m->E,
+                       (int64_t)m->faces.size(), m->G, m->N);
+    return hipGetLastError();
+}
+
+hipError_t run_dualgrad(const stdg_mesh* m, const double* p, double dt, double* w, hipStream_t s) {
+    if (fast_rows_supported(m)) return fast_dualgrad(m, p, dt, w, s);
+    const PicardDevice& d = m->pd;
+    const int64_t F = (int64_t)m->faces.size();
+    hipLaunchKernelGGL(k_dualgrad, dim3(nblk(3 * F * m->Nst)), dim3(256), 0, s, d.US, d.UN, m->d.cls, d.fl, d.flf, d.fr,
+                       d.TW, p, dt, w, F, m->G, m->N);
+    return hipGetLastError();
+}
+
+hipError_t run_rhs_pressure(const stdg_mesh* m, const double* Fv, double dt, double* b, hipStream_t s) {
+    if (fast_rows_supported(m)) return fast_rhs_pressure(m, Fv, dt, b, s);
+    hipLaunchKernelGGL(k_rhs_pressure, dim3(nblk(m->E * m->Nst)), dim3(256), 0, s, m->pd.QT, m->d.cls, m->pd.tet_face,
+                       m->pd.W, Fv, dt, b, m->E, (int64_t)m->faces.size(), m->G, m->N);
+    return hipGetLastError();
+}
+
+hipError_t run_visc_rhs(const stdg_mesh* m, const double* vprev, const double* ups, const double* lam,
+                        const double* vbc, double* rhs, hipStream_t s) {
+    if (fast_rows_supported(m)) return fast_visc_rhs(m, vprev, ups, lam, vbc, rhs, s);
+    const PicardDevice& d = m->pd;
+    hipLaunchKernelGGL(k_visc_rhs, dim3(nblk(3 * m->E * m->Nst)), dim3(256), 0, s, d.MIT, d.BB, m->d.cls, m->d.nbr,
+                       d.tet_face, d.g0g1, d.Tm, d.W, vprev, ups, lam, vbc, m->cfg.nu * m->cfg.dt, rhs, m->E,
+                       (int64_t)m->faces.size(), m->G, m->N);
+    return hipGetLastError();
+}
+
 template <int N, int G>
 static hipError_t launch_visc_ng(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
     const PicardDevice& d = m->pd;
@@ -512,6 +559,7 @@ hipError_t launch_visc_apply(const stdg_mesh* m, const double* x, double* y, hip
 }
 
 hipError_t launch_visc_precond(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
+    if (fast_blockdiag(m, x, y, s) == hipSuccess) return hipSuccess;
     const int NG = m->Nst;
     const int64_t n = 3 * m->E * NG;
     hipLaunchKernelGGL(k_blockdiag, dim3(nblk(n)), dim3(256), 0, s, m->pd.DV, m->d.cls, x, y, m->E, NG);
@@ -540,6 +588,17 @@ int upload_picard_tables(stdg_mesh* m) {
             for (int r = 0; r < N; ++r)
                 for (int c = 0; c < N; ++c) mit[blk * NN + (size_t)c * N + r] = t.MI[blk * NN + (size_t)r * N + c];
         if ((e = upload(d.SVt, svt)) || (e = upload(d.MIt, mit)) || (e = upload(d.DV, t.DV))) return e;
+        auto transposed = [&](const std::vector<double>& v) {
+            std::vector<double> o(v.size());
+            for (size_t blk = 0; blk < v.size() / NN; ++blk)
+                for (int r = 0; r < N; ++r)
+                    for (int c = 0; c < N; ++c) o[blk * NN + (size_t)c * N + r] = v[blk * NN + (size_t)r * N + c];
+            return o;
+        };
+        if ((e = upload(d.At, transposed(t.A))) || (e = upload(d.GBt, transposed(t.GB))) ||
+            (e = upload(d.QTt, transposed(t.QT))) || (e = upload(d.USt, transposed(t.US))) ||
+            (e = upload(d.UNt, transposed(t.UN))) || (e = upload(d.BBt, transposed(t.BB))))
+            return e;
     }
     const int64_t F = (int64_t)m->faces.size();
     std::vector<int64_t> fl(F), fr(F);
@@ -561,7 +620,8 @@ void free_picard(stdg_mesh* m) {
                     (void*)d.FW, (void*)d.PHv, (void*)d.dPHv, (void*)d.wv, (void*)d.tq, (void*)d.tw, (void*)d.gq,
                     (void*)d.Tm, (void*)d.TW, (void*)d.W, (void*)d.g0g1, (void*)d.g1, (void*)d.tet_face,
                     (void*)d.fl, (void*)d.fr, (void*)d.flf, (void*)d.frf, (void*)d.work, (void*)d.DV,
-                    (void*)d.SVt, (void*)d.MIt})
+                    (void*)d.SVt, (void*)d.MIt, (void*)d.At, (void*)d.GBt, (void*)d.QTt, (void*)d.USt,
+                    (void*)d.UNt, (void*)d.BBt})
         if (p) (void)hipFree(p);
     d = PicardDevice();
 }
@@ -589,9 +649,8 @@ extern "C" int stdg_dual_from_main(const stdg_mesh* m, const double* vbar, doubl
     if (!m->d.blocks || !m->pd.GB) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
     const int64_t F = (int64_t)m->faces.size();
     const int64_t n = 3 * F * m->Nst;
-    hipLaunchKernelGGL(k_goback, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, m->pd.GB, m->d.cls, m->pd.fl,
-                       m->pd.flf, m->pd.fr, m->pd.frf, vbar, vbar, vhat, (int64_t)0, F, F, m->E, m->G, m->N);
-    STDG_HIP(hipGetLastError());
+    (void)n;
+    STDG_HIP(run_goback(m, vbar, vbar, vhat, 0, F, (hipStream_t)stream));
     return STDG_OK;
 }
 
@@ -599,9 +658,8 @@ extern "C" int stdg_main_from_dual(const stdg_mesh* m, const double* vhat, doubl
     if (!m || !vbar || !vhat) { set_error("null argument"); return STDG_ERR_ARG; }
     if (!m->d.blocks || !m->pd.A) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
     const int64_t n = 3 * m->E * m->Nst;
-    hipLaunchKernelGGL(k_average, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, m->pd.A, m->d.cls,
-                       m->pd.tet_face, vhat, vbar, m->E, (int64_t)m->faces.size(), m->G, m->N);
-    STDG_HIP(hipGetLastError());
+    (void)n;
+    STDG_HIP(run_average(m, vhat, vbar, (hipStream_t)stream));
     return STDG_OK;
 }
 
@@ -610,9 +668,8 @@ extern "C" int stdg_divergence(const stdg_mesh* m, const double* vhat, double* d
     if (!m->d.blocks || !m->pd.QT) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
     // sum_j D_ij vhat_j = -sum_j Q_ij^T vhat_j
     const int64_t n = m->E * m->Nst;
-    hipLaunchKernelGGL(k_rhs_pressure, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, m->pd.QT, m->d.cls,
-                       m->pd.tet_face, m->pd.W, vhat, -m->cfg.dt, div, m->E, (int64_t)m->faces.size(), m->G, m->N);
-    STDG_HIP(hipGetLastError());
+    (void)n;
+    STDG_HIP(run_rhs_pressure(m, vhat, -m->cfg.dt, div, (hipStream_t)stream));
     return STDG_OK;
 }
 
@@ -673,8 +730,8 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     hipLaunchKernelGGL(k_zero, dim3(nblk(nD)), dim3(256), 0, s, vbc, nD);
     if (F > NI) {
         const int64_t nb = 3 * (F - NI) * G * N;
-        hipLaunchKernelGGL(k_goback, dim3(nblk(nb)), dim3(256), 0, s, d.GB, m->d.cls, d.fl, d.flf, d.fr, d.frf,
-                           g_nodal, g_nodal, vbc, NI, F, F, E, G, N);
+        (void)nb;
+        STDG_HIP(run_goback(m, g_nodal, g_nodal, vbc, NI, F, s));
         // boundary part of the iterate = prescribed data
         for (int c = 0; c < 3; ++c)
             hipLaunchKernelGGL(k_copyd, dim3(nblk((F - NI) * G * N)), dim3(256), 0, s,
@@ -691,14 +748,12 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     for (int k = 0; k < npic; ++k) {
         // step 1
         if (int e = stdg_main_from_dual(m, vk, vbk, s)) return e;
-        hipLaunchKernelGGL(k_dualgrad, dim3(nblk(nD)), dim3(256), 0, s, d.US, d.UN, m->d.cls, d.fl, d.flf, d.fr, d.TW,
-                           pk, dt, wg, F, G, N);
-        hipLaunchKernelGGL(k_average, dim3(nblk(nM)), dim3(256), 0, s, d.A, m->d.cls, d.tet_face, wg, lam, E, F, G, N);
+        STDG_HIP(run_dualgrad(m, pk, dt, wg, s));
+        STDG_HIP(run_average(m, wg, lam, s));
         // step 2
         CKP(launch_convection(m, vbk, vbc, ups, s));
         // step 3
-        hipLaunchKernelGGL(k_visc_rhs, dim3(nblk(nM)), dim3(256), 0, s, d.MIT, d.BB, m->d.cls, m->d.nbr, d.tet_face,
-                           d.g0g1, d.Tm, d.W, vprev, ups, lam, vbc, m->cfg.nu * dt, rhs, E, F, G, N);
+        STDG_HIP(run_visc_rhs(m, vprev, ups, lam, vbc, rhs, s));
         hipLaunchKernelGGL(k_copyd, dim3(nblk(nM)), dim3(256), 0, s, vbk, vhalf, nM);
         STDG_HIP(hipGetLastError());
         int vit = 0;
@@ -712,15 +767,13 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         viters += vit;
         vres = std::max(vres, vrel);
         // step 4
-        hipLaunchKernelGGL(k_goback, dim3(nblk(3 * NI * G * N)), dim3(256), 0, s, d.GB, m->d.cls, d.fl, d.flf, d.fr,
-                           d.frf, vhalf, vhalf, Fv, (int64_t)0, NI, F, E, G, N);
+        STDG_HIP(run_goback(m, vhalf, vhalf, Fv, 0, NI, s));
         for (int c = 0; c < 3 && F > NI; ++c)
             hipLaunchKernelGGL(k_copyd, dim3(nblk((F - NI) * G * N)), dim3(256), 0, s,
                                vbc + ((int64_t)c * F + NI) * G * N, Fv + ((int64_t)c * F + NI) * G * N,
                                (F - NI) * G * N);
         // step 5
-        hipLaunchKernelGGL(k_rhs_pressure, dim3(nblk(nP)), dim3(256), 0, s, d.QT, m->d.cls, d.tet_face, d.W, Fv, dt,
-                           bp, E, F, G, N);
+        STDG_HIP(run_rhs_pressure(m, Fv, dt, bp, s));
         STDG_HIP(hipStreamSynchronize(s));
         const auto tg0 = std::chrono::steady_clock::now();
         if (k == 0 && opts->rec_b)
@@ -757,8 +810,7 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
             first_res0 = prep.initial_rel_residual;
         }
         // step 6
-        hipLaunchKernelGGL(k_dualgrad, dim3(nblk(nD)), dim3(256), 0, s, d.US, d.UN, m->d.cls, d.fl, d.flf, d.fr, d.TW,
-                           dp, dt, wg, F, G, N);
+        STDG_HIP(run_dualgrad(m, dp, dt, wg, s));
         hipLaunchKernelGGL(k_update, dim3(nblk(nD)), dim3(256), 0, s, Fv, wg, vk, F, NI, G, N);
         hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, pk, dp, 1.0, nP);
         if (k == 0) {

@@ -1,0 +1,321 @@
+// Block-row kernels of the Picard step (Sec. 2.6, steps 1, 3, 4, 5 and the
+// viscous preconditioner): every output row of N coefficients is a sum of
+// small N x N operator blocks times gathered rows.  One thread computes one
+// row (entity, component or direction, time node) in registers.  Blocks are
+// stored per geometry class (and local face), column-major; elements are
+// class-chunked and faces sorted by their blocks' keys, so a wavefront
+// usually reads one block: then its columns arrive through scalar loads
+// broadcast to all lanes, otherwise each lane reads its own block.
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace stdg {
+namespace {
+
+// acc += s * B x with B column-major (column m at Bt + m N)
+template <int N>
+__device__ __forceinline__ void mv_acc(double (&acc)[N], const double* __restrict__ Bt, const double (&x)[N],
+                                       double s) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const double xm = s * x[m];
+#pragma unroll
+        for (int r = 0; r < N; ++r) acc[r] += Bt[m * N + r] * xm;
+    }
+}
+
+// acc += s * B(key) x, B(key) = base + key * N * N; scalar loads when the
+// whole wavefront has the same key
+template <int N>
+__device__ __forceinline__ void mv_key(double (&acc)[N], const double* __restrict__ base, int64_t key,
+                                       const double (&x)[N], double s) {
+    const int64_t k0 = __builtin_amdgcn_readfirstlane((int)key);
+    if (__all(key == k0)) {
+        mv_acc<N>(acc, base + k0 * N * N, x, s);
+    } else {
+        mv_acc<N>(acc, base + key * N * N, x, s);
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void load_row(double (&x)[N], const double* __restrict__ p) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) x[m] = p[m];
+}
+
+template <int N>
+__device__ __forceinline__ void store_row(double* __restrict__ p, const double (&x)[N], double s) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) p[m] = s * x[m];
+}
+
+// dual-grid pressure gradient (the factor of eq. prevpress and eq. A3_mod):
+// w[d][j][a] = dt sum_b TW[a][b] (US_{l,d} p_l[b] + UN_{l,d} p_r[b])
+template <int N>
+__global__ void __launch_bounds__(256) kf_dualgrad(const double* __restrict__ USt, const double* __restrict__ UNt,
+                                                   const int32_t* __restrict__ cls, const int64_t* __restrict__ fl,
+                                                   const int32_t* __restrict__ flf, const int64_t* __restrict__ fr,
+                                                   const double* __restrict__ TW, const double* __restrict__ p,
+                                                   double dt, double* __restrict__ w, int64_t F, int G) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * F * G) return;
+    const int a = (int)(t % G);
+    const int64_t j = (t / G) % F;
+    const int d = (int)(t / ((int64_t)G * F));
+    const int64_t l = fl[j], rr = fr[j];
+    const int64_t key = ((int64_t)cls[l] * 4 + flf[j]) * 3 + d;
+    double acc[N], x[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) acc[r] = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) x[m] = 0.0;
+    for (int b = 0; b < G; ++b) {
+        const double tw = TW[a * G + b];
+        const double* pl = p + (l * G + b) * N;
+#pragma unroll
+        for (int m = 0; m < N; ++m) x[m] += tw * pl[m];
+    }
+    mv_key<N>(acc, USt, key, x, 1.0);
+    if (rr >= 0) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) x[m] = 0.0;
+        for (int b = 0; b < G; ++b) {
+            const double tw = TW[a * G + b];
+            const double* pr = p + (rr * G + b) * N;
+#pragma unroll
+            for (int m = 0; m < N; ++m) x[m] += tw * pr[m];
+        }
+        mv_key<N>(acc, UNt, key, x, 1.0);
+    }
+    store_row<N>(w + ((d * F + j) * G + a) * N, acc, dt);
+}
+
+// eq. goback on faces f0 .. f1: out[c][j][a] = GB_l vbar_l[a] + GB_r vbar_r[a]
+// (boundary faces: one side, from vbdry)
+template <int N>
+__global__ void __launch_bounds__(256) kf_goback(const double* __restrict__ GBt, const int32_t* __restrict__ cls,
+                                                 const int64_t* __restrict__ fl, const int32_t* __restrict__ flf,
+                                                 const int64_t* __restrict__ fr, const int32_t* __restrict__ frf,
+                                                 const double* __restrict__ vbar, const double* __restrict__ vbdry,
+                                                 double* __restrict__ out, int64_t f0, int64_t f1, int64_t F,
+                                                 int64_t E, int G) {
+    const int64_t nf = f1 - f0;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * nf * G) return;
+    const int a = (int)(t % G);
+    const int64_t j = f0 + (t / G) % nf;
+    const int c = (int)(t / ((int64_t)G * nf));
+    const int64_t l = fl[j], rr = fr[j];
+    const double* src = rr >= 0 ? vbar : vbdry;
+    double acc[N], x[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) acc[r] = 0.0;
+    load_row<N>(x, src + ((c * E + l) * G + a) * N);
+    mv_key<N>(acc, GBt, (int64_t)cls[l] * 4 + flf[j], x, 1.0);
+    if (rr >= 0) {
+        load_row<N>(x, vbar + ((c * E + rr) * G + a) * N);
+        mv_key<N>(acc, GBt, (int64_t)cls[rr] * 4 + frf[j], x, 1.0);
+    }
+    store_row<N>(out + ((c * F + j) * G + a) * N, acc, 1.0);
+}
+
+// eq. average: vbar[c][i][a] = sum_f A_{i,f} vhat[c][face(i,f)][a]
+template <int N>
+__global__ void __launch_bounds__(256) kf_average(const double* __restrict__ At, const int32_t* __restrict__ cls,
+                                                  const int64_t* __restrict__ tet_face,
+                                                  const double* __restrict__ vhat, double* __restrict__ vbar,
+                                                  int64_t E, int64_t F, int G) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * E * G) return;
+    const int a = (int)(t % G);
+    const int64_t i = (t / G) % E;
+    const int c = (int)(t / ((int64_t)G * E));
+    double acc[N], x[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) acc[r] = 0.0;
+    for (int f = 0; f < 4; ++f) {
+        load_row<N>(x, vhat + ((c * F + tet_face[4 * i + f]) * G + a) * N);
+        mv_key<N>(acc, At, (int64_t)cls[i] * 4 + f, x, 1.0);
+    }
+    store_row<N>(vbar + ((c * E + i) * G + a) * N, acc, 1.0);
+}
+
+// pressure right-hand side (eq. A2_mod): b[i][a] = dt W_a sum_{f,d} Q^T_{i,f,d} Fv[d][face][a]
+template <int N>
+__global__ void __launch_bounds__(256) kf_rhs_pressure(const double* __restrict__ QTt, const int32_t* __restrict__ cls,
+                                                       const int64_t* __restrict__ tet_face,
+                                                       const double* __restrict__ W, const double* __restrict__ Fv,
+                                                       double dt, double* __restrict__ b, int64_t E, int64_t F,
+                                                       int G) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= E * G) return;
+    const int a = (int)(t % G);
+    const int64_t i = t / G;
+    double acc[N], x[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) acc[r] = 0.0;
+    for (int f = 0; f < 4; ++f) {
+        const int64_t j = tet_face[4 * i + f];
+        for (int d = 0; d < 3; ++d) {
+            load_row<N>(x, Fv + ((d * F + j) * G + a) * N);
+            mv_key<N>(acc, QTt, ((int64_t)cls[i] * 4 + f) * 3 + d, x, 1.0);
+        }
+    }
+    store_row<N>(b + (i * G + a) * N, acc, dt * W[a]);
+}
+
+// viscous right-hand side (eq. A1_mod):
+// rhs = M (sum_b g0g1[a][b] vprev_b - T[a][b] lam_b) - ups_a - nu dt W_a sum_{bdry f} BB_f vbc
+template <int N>
+__global__ void __launch_bounds__(256) kf_visc_rhs(const double* __restrict__ MIt, const double* __restrict__ BBt,
+                                                   const int32_t* __restrict__ cls, const int32_t* __restrict__ nbr,
+                                                   const int64_t* __restrict__ tet_face,
+                                                   const double* __restrict__ g0g1, const double* __restrict__ Tm,
+                                                   const double* __restrict__ W, const double* __restrict__ vprev,
+                                                   const double* __restrict__ ups, const double* __restrict__ lam,
+                                                   const double* __restrict__ vbc, double nu_dt,
+                                                   double* __restrict__ rhs, int64_t E, int64_t F, int G) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * E * G) return;
+    const int a = (int)(t % G);
+    const int64_t i = (t / G) % E;
+    const int c = (int)(t / ((int64_t)G * E));
+    double acc[N], x[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) acc[r] = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) x[m] = 0.0;
+    for (int b = 0; b < G; ++b) {
+        const double g = g0g1[a * G + b], tm = Tm[a * G + b];
+        const double* xp = vprev + ((c * E + i) * G + b) * N;
+        const double* xl = lam + ((c * E + i) * G + b) * N;
+#pragma unroll
+        for (int m = 0; m < N; ++m) x[m] += g * xp[m] - tm * xl[m];
+    }
+    mv_key<N>(acc, MIt, cls[i], x, 1.0);
+    const double* up = ups + ((c * E + i) * G + a) * N;
+#pragma unroll
+    for (int r = 0; r < N; ++r) acc[r] -= up[r];
+    for (int f = 0; f < 4; ++f) {
+        // boundary faces only: a wavefront of interior elements skips this
+        if (nbr[4 * i + f] >= 0) continue;
+        load_row<N>(x, vbc + ((c * F + tet_face[4 * i + f]) * G + a) * N);
+        mv_acc<N>(acc, BBt + ((int64_t)cls[i] * 4 + f) * N * N, x, -nu_dt * W[a]);
+    }
+    store_row<N>(rhs + ((c * E + i) * G + a) * N, acc, 1.0);
+}
+
+// y = D^-1 x for the viscous block-Jacobi preconditioner: one thread per
+// (component, element) applies the element's NG x NG inverse block (DV
+// column-major per class).
+template <int NG>
+__global__ void __launch_bounds__(256) kf_blockdiag(const double* __restrict__ DV, const int32_t* __restrict__ cls,
+                                                    const double* __restrict__ x, double* __restrict__ y, int64_t E) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * E) return;
+    const int64_t i = t % E;
+    double acc[NG], xv[NG];
+#pragma unroll
+    for (int r = 0; r < NG; ++r) acc[r] = 0.0;
+    load_row<NG>(xv, x + t * NG);
+    mv_key<NG>(acc, DV, cls[i], xv, 1.0);
+    store_row<NG>(y + t * NG, acc, 1.0);
+}
+
+inline unsigned nb(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 255) / 256); }
+
+template <int N>
+struct Launch {
+    static hipError_t dualgrad(const stdg_mesh* m, const double* p, double dt, double* w, hipStream_t s) {
+        const PicardDevice& d = m->pd;
+        const int64_t F = (int64_t)m->faces.size();
+        hipLaunchKernelGGL(kf_dualgrad<N>, dim3(nb(3 * F * m->G)), dim3(256), 0, s, d.USt, d.UNt, m->d.cls, d.fl,
+                           d.flf, d.fr, d.TW, p, dt, w, F, m->G);
+        return hipGetLastError();
+    }
+    static hipError_t goback(const stdg_mesh* m, const double* vbar, const double* vbdry, double* out, int64_t f0,
+                             int64_t f1, hipStream_t s) {
+        const PicardDevice& d = m->pd;
+        const int64_t F = (int64_t)m->faces.size();
+        if (f1 <= f0) return hipSuccess;
+        hipLaunchKernelGGL(kf_goback<N>, dim3(nb(3 * (f1 - f0) * m->G)), dim3(256), 0, s, d.GBt, m->d.cls, d.fl,
+                           d.flf, d.fr, d.frf, vbar, vbdry, out, f0, f1, F, m->E, m->G);
+        return hipGetLastError();
+    }
+    static hipError_t average(const stdg_mesh* m, const double* vhat, double* vbar, hipStream_t s) {
+        const PicardDevice& d = m->pd;
+        hipLaunchKernelGGL(kf_average<N>, dim3(nb(3 * m->E * m->G)), dim3(256), 0, s, d.At, m->d.cls, d.tet_face,
+                           vhat, vbar, m->E, (int64_t)m->faces.size(), m->G);
+        return hipGetLastError();
+    }
+    static hipError_t rhs_pressure(const stdg_mesh* m, const double* Fv, double dt, double* b, hipStream_t s) {
+        const PicardDevice& d = m->pd;
+        hipLaunchKernelGGL(kf_rhs_pressure<N>, dim3(nb(m->E * m->G)), dim3(256), 0, s, d.QTt, m->d.cls, d.tet_face,
+                           d.W, Fv, dt, b, m->E, (int64_t)m->faces.size(), m->G);
+        return hipGetLastError();
+    }
+    static hipError_t visc_rhs(const stdg_mesh* m, const double* vprev, const double* ups, const double* lam,
+                               const double* vbc, double* rhs, hipStream_t s) {
+        const PicardDevice& d = m->pd;
+        hipLaunchKernelGGL(kf_visc_rhs<N>, dim3(nb(3 * m->E * m->G)), dim3(256), 0, s, d.MIt, d.BBt, m->d.cls,
+                           m->d.nbr, d.tet_face, d.g0g1, d.Tm, d.W, vprev, ups, lam, vbc, m->cfg.nu * m->cfg.dt, rhs,
+                           m->E, (int64_t)m->faces.size(), m->G);
+        return hipGetLastError();
+    }
+};
+
+template <int NG>
+hipError_t blockdiag_ng(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(kf_blockdiag<NG>, dim3(nb(3 * m->E)), dim3(256), 0, s, m->pd.DV, m->d.cls, x, y, m->E);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define STDG_FAST_N(CALL)                          \
+    switch (m->N) {                                \
+        case 4: return Launch<4>::CALL;            \
+        case 10: return Launch<10>::CALL;          \
+        case 20: return Launch<20>::CALL;          \
+        case 35: return Launch<35>::CALL;          \
+        default: return hipErrorNotSupported;      \
+    }
+
+bool fast_rows_supported(const stdg_mesh* m) { return m->N == 4 || m->N == 10 || m->N == 20 || m->N == 35; }
+
+hipError_t fast_dualgrad(const stdg_mesh* m, const double* p, double dt, double* w, hipStream_t s) {
+    STDG_FAST_N(dualgrad(m, p, dt, w, s))
+}
+hipError_t fast_goback(const stdg_mesh* m, const double* vbar, const double* vbdry, double* out, int64_t f0,
+                       int64_t f1, hipStream_t s) {
+    STDG_FAST_N(goback(m, vbar, vbdry, out, f0, f1, s))
+}
+hipError_t fast_average(const stdg_mesh* m, const double* vhat, double* vbar, hipStream_t s) {
+    STDG_FAST_N(average(m, vhat, vbar, s))
+}
+hipError_t fast_rhs_pressure(const stdg_mesh* m, const double* Fv, double dt, double* b, hipStream_t s) {
+    STDG_FAST_N(rhs_pressure(m, Fv, dt, b, s))
+}
+hipError_t fast_visc_rhs(const stdg_mesh* m, const double* vprev, const double* ups, const double* lam,
+                         const double* vbc, double* rhs, hipStream_t s) {
+    STDG_FAST_N(visc_rhs(m, vprev, ups, lam, vbc, rhs, s))
+}
+#undef STDG_FAST_N
+
+// NG = N G up to 40 (p <= 3 with p_gamma <= 1, or p <= 2 with p_gamma <= 3)
+hipError_t fast_blockdiag(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
+    switch (m->Nst) {
+        case 4: return blockdiag_ng<4>(m, x, y, s);
+        case 8: return blockdiag_ng<8>(m, x, y, s);
+        case 10: return blockdiag_ng<10>(m, x, y, s);
+        case 12: return blockdiag_ng<12>(m, x, y, s);
+        case 16: return blockdiag_ng<16>(m, x, y, s);
+        case 20: return blockdiag_ng<20>(m, x, y, s);
+        case 30: return blockdiag_ng<30>(m, x, y, s);
+        case 40: return blockdiag_ng<40>(m, x, y, s);
+        default: return hipErrorNotSupported;
+    }
+}
+
+}  // namespace stdg
