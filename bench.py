@@ -15,13 +15,16 @@ the plain-vs-chosen pressure-solve comparison.
 
 `value` is the whole-job Schur-operator throughput: pressure-operator
 applications in the timed steps x DoF / timed wall time (GDoF/s).  The
-roofline entry is for the step's dominant kernel, the fused FP32 CG operator
-kernel (p = r + beta p, q = (B (x) I) p on MFMA, partial p.q), timed with HIP
-events on the library's stream over a burst of launches through
-stdg_pressure_apply_spatial_f32 (the same kernel with beta = 0) right after
-the timed steps.  Algorithmic bytes per launch: read r and p, write p and q
-once (4 x 4 B per DoF) plus 20 B of indices per element; flops: 2 N^2 x 5
-blocks per column.  The FP64 Schur apply is timed the same way (context).
+roofline entry is for the step's dominant kernel, the one-kernel FP32 CG
+iteration k_cg_op<N, true> (r, p updates while staging the operand panels,
+q = (B (x) I) p on MFMA, x update, four dot-product partials).  Its duration
+is the library's own HIP-event measurement on its stream around the
+back-to-back iteration launches of every inner solve of the timed steps
+(stdg_step_report.pressure_fused_iter_us).  Algorithmic bytes per launch:
+read r, p, q, x and write r, p, q, x once (8 x 4 B per DoF) plus 20 B of
+indices per element; flops: 2 N^2 x 5 blocks per column.  The plain FP32
+operator kernel (stdg_pressure_apply_spatial_f32) and the FP64 Schur apply
+are timed with HIP events over bursts of launches (context).
 """
 
 import argparse
@@ -145,10 +148,12 @@ def main():
     dofs = E * Nst
     flops = 2.0 * N * N * G * 5 * E + 2.0 * N * G * G * E          # 5 N x N blocks x G columns + time mix
     bytes_alg = 2.0 * dofs * 8 + 20.0 * E                           # x and y once, 5 int32 indices
-    # fused FP32 CG operator kernel (B (x) I): r, p read, p, q written once
-    k_bytes = 4.0 * dofs * 4 + 20.0 * E
+    # one-kernel FP32 CG iteration (B (x) I): r, p, q, x read and written once
+    it_us = sum(r.pressure_fused_iter_us * r.pressure_iters for r in reps) / max(
+        sum(r.pressure_iters for r in reps if r.pressure_fused_iter_us > 0), 1)
+    k_bytes = 8.0 * dofs * 4 + 20.0 * E
     k_flops = 2.0 * N * N * 5 * E * G
-    k_s = k_us * 1e-6 if k_us > 0 else float("nan")
+    k_s = it_us * 1e-6 if it_us > 0 else float("nan")
 
     # ---- plain form from the state before the timed steps
     plain_rep = None
@@ -193,7 +198,10 @@ def main():
                               "hbm_gbs_algorithmic": bytes_alg / t_apply / 1e9},
         "roofline": {"bound": "hbm", "achieved": k_bytes / k_s / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": k_bytes / k_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_cg_spmv<{N}>", "kernel_us": k_us, "kernel_launches": args.applies,
+                     "kernel": f"k_cg_op<{N},true>", "kernel_us": it_us,
+                     "kernel_launches": sum(r.pressure_iters for r in reps),
+                     "plain_operator_kernel": {"kernel": f"k_cg_op<{N},false>", "us": k_us,
+                                               "launches": args.applies},
                      "bytes_per_launch": k_bytes, "flops_per_launch": k_flops,
                      "mfma_tflops": k_flops / k_s / 1e12,
                      "mfma_frac_fp32": k_flops / k_s / 1e12 / FP32_MFMA_PEAK_TFLOPS},

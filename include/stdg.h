@@ -168,6 +168,9 @@ typedef struct {
     double rel_residual;   /* ||b_a - S_a x|| / ||b_a|| in FP64 at exit        */
     double seconds;        /* wall time of the call                            */
     double initial_rel_residual;  /* the same for the initial guess            */
+    double fused_iter_us;  /* device time per iteration of the one-kernel FP32 */
+                           /* CG (HIP events around its back-to-back launches;  */
+                           /* 0 when that kernel did not run)                  */
 } stdg_solve_report;
 
 /* y = (B (x) I) x in FP32: the spatial Schur operator B = dt^2 S^sp of
@@ -250,6 +253,7 @@ typedef struct {
     int32_t first_pressure_iters;      /* iterations of the first solve       */
     double first_pressure_seconds;     /* its time, guess included            */
     double first_initial_residual;     /* ||b - S x0|| / ||b|| of its guess   */
+    double pressure_fused_iter_us;     /* fused_iter_us over the step's solves */
 } stdg_step_report;
 
 /* Defaults: n_picard 0, zero pressure guess, solve defaults, viscous rtol

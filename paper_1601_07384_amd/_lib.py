@@ -52,7 +52,7 @@ class SolveReport(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
                 ("inner_iters", ctypes.c_int32), ("applies", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("initial_rel_residual", ctypes.c_double)]
+                ("initial_rel_residual", ctypes.c_double), ("fused_iter_us", ctypes.c_double)]
 
 
 STDG_GUESS_ZERO = 0
@@ -78,7 +78,8 @@ class StepReport(ctypes.Structure):
                 ("pressure_seconds", ctypes.c_double), ("viscous_seconds", ctypes.c_double),
                 ("pressure_applies", ctypes.c_int32), ("first_pressure_iters", ctypes.c_int32),
                 ("first_pressure_seconds", ctypes.c_double),
-                ("first_initial_residual", ctypes.c_double)]
+                ("first_initial_residual", ctypes.c_double),
+                ("pressure_fused_iter_us", ctypes.c_double)]
 
 
 class ModelConfig(ctypes.Structure):

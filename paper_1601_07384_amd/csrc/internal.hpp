@@ -52,8 +52,10 @@ struct Workspace {
     float* r32 = nullptr; float* p32 = nullptr; float* q32 = nullptr; float* x32 = nullptr;
     float* b32 = nullptr;
     float* V32 = nullptr;         // FP32 GMRES basis
-    float* p32b = nullptr;        // second FP32 search direction (fused CG)
-    hipEvent_t ev[2] = {nullptr, nullptr};   // samples the operator kernel's duration
+    float* p32b = nullptr;        // second buffers of r, p, q (one-kernel CG iteration)
+    float* r32b = nullptr;
+    float* q32b = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // residual checks, loop timing
     double* partial = nullptr;    // reduction partials
     double* scal = nullptr;       // device scalars (small)
     double* hscal = nullptr;      // pinned host mirror

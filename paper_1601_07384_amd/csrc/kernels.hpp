@@ -19,13 +19,14 @@ hipError_t launch_apply_f64_c(const stdg_mesh* m, const double* C, const double*
 hipError_t launch_apply_f32_c(const stdg_mesh* m, const float* C, const float* x, float* y, hipStream_t s);
 constexpr int CG_UPD_BLOCKS = 1024;
 bool cg_fused_supported(const stdg_mesh* m);
-int64_t cg_spmv_blocks(const stdg_mesh* m);
-hipError_t launch_cg_spmv_f32(const stdg_mesh* m, const float* r, const float* pold, float* pnew, float* q,
-                              double* scal, int s_rr, int iter, float cscale, const double* upart,
-                              int64_t n_upart, double* spart, hipStream_t s);
-hipError_t launch_cg_upd_f32(float* x, float* r, const float* p, const float* q, const double* scal, int s_rr,
-                             int iter, int64_t n, const double* spart, int64_t n_spart, double* upart,
-                             hipStream_t s);
+int64_t cg_op_blocks(const stdg_mesh* m);
+hipError_t launch_cg_iter_f32(const stdg_mesh* m, float* x, const float* r_in, const float* p_in, const float* q_in,
+                              float* r_out, float* p_out, float* q_out, int iter, float cscale,
+                              const double* part_in, int64_t n_in, double* part_out, double* ab, hipStream_t s);
+hipError_t launch_cg_apply_f32(const stdg_mesh* m, const float* x, float* y, float cscale, hipStream_t s);
+hipError_t launch_cg_tail_f32(float* x, const float* p, int64_t n, const double* part, int64_t n_part,
+                              hipStream_t s);
+hipError_t launch_cg_check_f32(const double* part, int64_t n_part, double* scal, int slot, hipStream_t s);
 hipError_t time_mix_f64(const stdg_mesh* m, const double* M, const double* x, double* y, hipStream_t s);
 hipError_t time_mix_f32(const stdg_mesh* m, const float* M, const float* x, float* y, hipStream_t s);
 hipError_t launch_visc_apply(const stdg_mesh* m, const double* x, double* y, hipStream_t s);

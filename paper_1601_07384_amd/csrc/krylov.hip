@@ -337,6 +337,8 @@ struct Ctx {
                        // 2: B (x) I, 3: block-Jacobi preconditioned viscous operator D^-1 A
     double* tmp = nullptr;   // op 3: holds A x before D^-1
     int applies = 0;
+    double loop_ms = 0.0;    // device time of the one-kernel CG iterations (HIP events)
+    int loop_iters = 0;
 };
 
 template <typename T> struct Apply;
@@ -386,12 +388,11 @@ int time_sums(Ctx& c, const double* v) {
     return STDG_OK;
 }
 
-// FP32 CG with the fused two-kernel iteration (operator B (x) I only).
+// FP32 CG with the one-kernel iteration (operator B (x) I only).
 bool cg_fusable(const Ctx& c) {
     const stdg_mesh* m = c.m;
-    static_assert(CG_UPD_BLOCKS == NBLK, "the update kernel's partials share the residual layout");
-    return (c.op == 2 || (c.op == 0 && m->G == 1)) && cg_fused_supported(m) && m->ws.p32b &&
-           NBLK + cg_spmv_blocks(m) <= (int64_t)NBLK * 208;
+    return (c.op == 2 || (c.op == 0 && m->G == 1)) && cg_fused_supported(m) && m->ws.p32b && m->ws.r32b &&
+           m->ws.q32b && 8 * cg_op_blocks(m) <= (int64_t)NBLK * 208;
 }
 
 int cg_fused(Ctx& c, const float* b, float* x, float* r, float* p, float* q, double tol_abs, int max_it,
@@ -399,19 +400,21 @@ int cg_fused(Ctx& c, const float* b, float* x, float* r, float* p, float* q, dou
     const stdg_mesh* m = c.m;
     const int64_t n = c.n;
     const int gb = grid_for(n);
-    float* pa = p;
-    float* pb = m->ws.p32b;
+    float* rb[2] = {r, m->ws.r32b};
+    float* pb[2] = {p, m->ws.p32b};
+    float* qb[2] = {q, m->ws.q32b};
+    const int64_t nb = cg_op_blocks(m);
+    double* part[2] = {c.partial, c.partial + 4 * nb};
     const float cscale = c.op == 2 ? 1.0f : (float)m->Ctime[0];
-    double* upart = c.partial;                   // NBLK partials of r.r
-    double* spart = c.partial + NBLK;            // operator-kernel partials of p.q
-    const int64_t nsp = cg_spmv_blocks(m);
-    CK(Apply<float>::run(c, x, q)); c.applies++;
-    hipLaunchKernelGGL((k_resid<float, float>), dim3(NBLK), dim3(RT), 0, c.s, b, q, r, n, upart);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, upart, NBLK, c.scal, (int)S_TMP, (int)FIN_STORE);
-    hipLaunchKernelGGL(k_fill<float>, dim3(gb), dim3(256), 0, c.s, pa, 0.0f, n);
+    // r_0 = b - A x, rr_0 into the even rr slot; p_{-1} = q_{-1} = 0
+    CK(Apply<float>::run(c, x, qb[1])); c.applies++;
+    hipLaunchKernelGGL((k_resid<float, float>), dim3(NBLK), dim3(RT), 0, c.s, b, qb[1], rb[0], n, c.partial);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_FRR, (int)FIN_STORE);
+    hipLaunchKernelGGL(k_fill<float>, dim3(gb), dim3(256), 0, c.s, pb[0], 0.0f, n);
+    hipLaunchKernelGGL(k_fill<float>, dim3(gb), dim3(256), 0, c.s, qb[0], 0.0f, n);
     CK(hipGetLastError());
     double rr;
-    if (int e = read_scal(c, S_TMP, rr)) return e;
+    if (int e = read_scal(c, S_FRR, rr)) return e;
     iters = 0;
     res_out = std::sqrt(rr);
     if (res_out <= tol_abs) return STDG_OK;
@@ -420,10 +423,9 @@ int cg_fused(Ctx& c, const float* b, float* x, float* r, float* p, float* q, dou
     // so the device queue never drains while the host waits.  A solve thus
     // runs up to check_every iterations past the one that met the tolerance.
     hipEvent_t const* ev = m->ws.ev;
-    int slot = 0, pending = -1;
+    int slot = 0, pending = -1, status = STDG_NOT_CONVERGED;
     auto enqueue_check = [&](int sl) -> int {
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, upart, NBLK, c.scal, (int)S_CHK + sl,
-                           (int)FIN_STORE);
+        CK(launch_cg_check_f32(part[(iters - 1) & 1], nb, c.scal, (int)S_CHK + sl, c.s));
         CK(hipMemcpyAsync(c.hscal + 2 + sl, c.scal + S_CHK + sl, sizeof(double), hipMemcpyDeviceToHost, c.s));
         CK(hipEventRecord(ev[sl], c.s));
         return STDG_OK;
@@ -434,33 +436,41 @@ int cg_fused(Ctx& c, const float* b, float* x, float* r, float* p, float* q, dou
         if (!std::isfinite(v)) { set_error("non-finite residual in CG"); return STDG_ERR_NUMERIC; }
         return STDG_OK;
     };
-    while (iters < max_it) {
-        CK(launch_cg_spmv_f32(m, r, pa, pb, q, c.scal, S_FRR, iters, cscale, upart, NBLK, spart, c.s));
+    const hipEvent_t t0ev = m->ws.ev[2], t1ev = m->ws.ev[3];
+    CK(hipEventRecord(t0ev, c.s));
+    while (iters < max_it && status != STDG_OK) {
+        const int i = iters, in = i & 1, out = in ^ 1;
+        CK(launch_cg_iter_f32(m, x, rb[in], pb[in], qb[in], rb[out], pb[out], qb[out], i, cscale, part[out], nb,
+                              part[in], c.scal + S_FRR, c.s));
         c.applies++;
-        CK(launch_cg_upd_f32(x, r, pb, q, c.scal, S_FRR, iters, n, spart, nsp, upart, c.s));
-        std::swap(pa, pb);
         ++iters;
         if (iters % check_every == 0 || iters == max_it) {
             if (int e = enqueue_check(slot)) return e;
             if (pending >= 0) {
                 if (int e = read_check(slot ^ 1, rr)) return e;
-                if (std::sqrt(rr) <= tol_abs) {
-                    // converged at the previous check; report the newest residual
-                    if (int e = read_check(slot, rr)) return e;
-                    res_out = std::sqrt(rr);
-                    return STDG_OK;
-                }
+                if (std::sqrt(rr) <= tol_abs) status = STDG_OK;
             }
             pending = iters;
             slot ^= 1;
         }
     }
+    CK(hipEventRecord(t1ev, c.s));
+    if (iters == 0) return STDG_NOT_CONVERGED;
+    // x += alpha p of the last iteration, then the newest residual
+    CK(launch_cg_tail_f32(x, pb[iters & 1], n, part[(iters - 1) & 1], nb, c.s));
+    {
+        float ms = 0.0f;
+        CK(hipEventSynchronize(t1ev));
+        CK(hipEventElapsedTime(&ms, t0ev, t1ev));
+        c.loop_ms += ms;
+        c.loop_iters += iters;
+    }
     if (pending >= 0) {
         if (int e = read_check(slot ^ 1, rr)) return e;
         res_out = std::sqrt(rr);
-        if (res_out <= tol_abs) return STDG_OK;
+        if (res_out <= tol_abs) status = STDG_OK;
     }
-    return STDG_NOT_CONVERGED;
+    return status;
 }
 
 // CG on S x = b (consistent); x, b, work vectors of type T.  Stops when the
@@ -597,12 +607,10 @@ int ensure_workspace(stdg_mesh* m, int mres, bool need32) {
         STDG_HIP(hipHostMalloc(&w.hscal, sizeof(double) * 8));
     }
     if (need32) {
-        for (float** f : {&w.r32, &w.p32, &w.q32, &w.x32, &w.b32, &w.p32b})
+        for (float** f : {&w.r32, &w.p32, &w.q32, &w.x32, &w.b32, &w.p32b, &w.r32b, &w.q32b})
             if (!*f) STDG_HIP(hipMalloc(f, n * sizeof(float)));
-        if (!w.ev[0]) {
-            STDG_HIP(hipEventCreate(&w.ev[0]));
-            STDG_HIP(hipEventCreate(&w.ev[1]));
-        }
+        if (!w.ev[0])
+            for (hipEvent_t& e : w.ev) STDG_HIP(hipEventCreate(&e));
     }
     if (mres > w.restart) {
         if (w.V) STDG_HIP(hipFree(w.V));
@@ -621,7 +629,7 @@ void free_workspace(stdg_mesh* m) {
     Workspace& w = m->ws;
     for (void* p : {(void*)w.r, (void*)w.p, (void*)w.q, (void*)w.z, (void*)w.V, (void*)w.r32, (void*)w.p32,
                     (void*)w.q32, (void*)w.x32, (void*)w.b32, (void*)w.V32, (void*)w.partial, (void*)w.scal,
-                    (void*)w.p32b})
+                    (void*)w.p32b, (void*)w.r32b, (void*)w.q32b})
         if (p) (void)hipFree(p);
     if (w.hscal) (void)hipHostFree(w.hscal);
     for (hipEvent_t e : w.ev)
@@ -849,22 +857,19 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
         rep->applies = c.applies;
         rep->rel_residual = rel;
         rep->initial_rel_residual = rel0;
+        rep->fused_iter_us = c.loop_iters ? 1e3 * c.loop_ms / c.loop_iters : 0.0;
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;
 }
 
-// y = (B (x) I) x in FP32 with the fused CG operator kernel (beta = 0).
+// y = (B (x) I) x in FP32 with the CG operator kernel.
 extern "C" int stdg_pressure_apply_spatial_f32(const stdg_mesh* cm, const float* x, float* y, void* stream) {
     if (!cm || !x || !y) { set_error("null argument"); return STDG_ERR_ARG; }
     stdg_mesh* m = const_cast<stdg_mesh*>(cm);
     if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
     if (!cg_fused_supported(m)) { set_error("the FP32 spatial operator kernel supports p = 1, 2, 3"); return STDG_ERR_ARG; }
-    if (int e = ensure_workspace(m, 0, true)) return e;
-    Workspace& w = m->ws;
-    if (NBLK + cg_spmv_blocks(m) > (int64_t)NBLK * 208) { set_error("mesh too large for the reduction buffer"); return STDG_ERR_ARG; }
-    const hipError_t e = launch_cg_spmv_f32(m, x, x, w.p32b, y, w.scal, S_FRR, 0, 1.0f, w.partial, NBLK,
-                                           w.partial + NBLK, (hipStream_t)stream);
+    const hipError_t e = launch_cg_apply_f32(m, x, y, 1.0f, (hipStream_t)stream);
     if (e != hipSuccess) { set_error(std::string("spatial apply: ") + hipGetErrorString(e)); return STDG_ERR_DEVICE; }
     return STDG_OK;
 }

@@ -744,6 +744,7 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         hipLaunchKernelGGL(k_zero, dim3(nblk(nP)), dim3(256), 0, s, pk, nP);
     STDG_HIP(hipGetLastError());
     int piters = 0, viters = 0, papplies = 0, first_iters = 0;
+    double fused_us_sum = 0.0, fused_w = 0.0;
     double pres = 0.0, vres = 0.0, psec = 0.0, vsec = 0.0, first_sec = 0.0, first_res0 = 0.0;
     for (int k = 0; k < npic; ++k) {
         // step 1
@@ -802,6 +803,8 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         if (e < 0) return e;
         piters += prep.inner_iters;
         papplies += prep.applies;
+        fused_us_sum += prep.fused_iter_us * prep.inner_iters;
+        fused_w += prep.fused_iter_us > 0.0 ? prep.inner_iters : 0;
         psec += prep.seconds + guess_sec;
         pres = std::max(pres, prep.rel_residual);
         if (k == 0) {
@@ -839,6 +842,7 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         rep->first_pressure_iters = first_iters;
         rep->first_pressure_seconds = first_sec;
         rep->first_initial_residual = first_res0;
+        rep->pressure_fused_iter_us = fused_w > 0.0 ? fused_us_sum / fused_w : 0.0;
     }
     return STDG_OK;
 }
