@@ -143,3 +143,36 @@ def guess(theta, P, Pm, B, nbr, hidden):
     Y, _ = forward(theta, F, hidden, P.shape[1])
     P = np.asarray(P, dtype=np.float64)
     return (2.0 * P - Pm) + rms(P - Pm) * Y
+
+
+def residual_loss_and_grad(theta, F, P, Pm, X, S, hidden):
+    """Residual-norm training objective of the learned guess.
+
+    With the extrapolation x_e = 2P - Pm, the guess x0 = x_e + s_D MLP(F) and
+    the operator S of the solve (a matrix acting on flattened (E, Nst)
+    vectors):  L = |S (x0 - x*)|^2 / |S (x_e - x*)|^2, the initial residual of
+    the solve relative to that of plain extrapolation.  Returns L and dL/dtheta
+    (chain rule: dL/dY = s_D 2 S^T S (x0 - x*) / |S (x_e - x*)|^2, then the
+    network's backward pass)."""
+    P = np.asarray(P, dtype=np.float64)
+    Pm = np.asarray(Pm, dtype=np.float64)
+    E, nst = P.shape
+    sD = rms(P - Pm)
+    W1, b1, W2, b2, W3, b3 = unflatten(theta, F.shape[1], hidden, nst)
+    Y, (F, Z1, H1, Z2, H2) = forward(theta, F, hidden, nst)
+    ee = (2.0 * P - Pm - X).ravel()
+    Re = S @ ee
+    den = float(Re @ Re)
+    e = ee + sD * Y.ravel()
+    R = S @ e
+    loss = float(R @ R) / den
+    dY = (sD * 2.0 * (S.T @ R) / den).reshape(E, nst)
+    gW3 = H2.T @ dY
+    gb3 = dY.sum(axis=0)
+    dZ2 = (dY @ W3.T) * silu_prime(Z2)
+    gW2 = H1.T @ dZ2
+    gb2 = dZ2.sum(axis=0)
+    dZ1 = (dZ2 @ W2.T) * silu_prime(Z1)
+    gW1 = F.T @ dZ1
+    gb1 = dZ1.sum(axis=0)
+    return loss, flatten([gW1, gb1, gW2, gb2, gW3, gb3])

@@ -11,6 +11,9 @@
 * Feature gather: the neighbour slots hold the values of the element sharing
   the face opposite each local vertex, found by brute force over all
   elements; flags are 0 exactly on boundary faces; scales are RMS values.
+* Residual-norm objective: equals 1 when the network outputs zero (the guess
+  is the plain extrapolation), 0 when it outputs the exact correction, and
+  its gradient matches central finite differences.
 """
 
 import numpy as np
@@ -165,3 +168,37 @@ def test_adam_reduces_loss_on_a_linear_target():
         theta, m, v = mlp.adam_step(theta, g, m, v, t, lr=1e-2)
     l1, _ = mlp.loss_and_grad(theta, F, T, hidden, n_out)
     assert l1 < 0.05 * l0
+
+
+def test_residual_loss_closed_forms_and_gradient():
+    rng = np.random.default_rng(11)
+    E, nst, hidden = 6, 3, 5
+    n_in = 8
+    S = rng.standard_normal((E * nst, E * nst))
+    P = rng.standard_normal((E, nst))
+    Pm = P - 0.1 * rng.standard_normal((E, nst))
+    X = 2 * P - Pm + 0.05 * rng.standard_normal((E, nst))
+    F = rng.standard_normal((E, n_in))
+    sD = np.sqrt(np.mean((P - Pm) ** 2))
+    zero = np.zeros(sum(int(np.prod(s)) for s in mlp.shapes(n_in, hidden, nst)))
+    loss0, _ = mlp.residual_loss_and_grad(zero, F, P, Pm, X, S, hidden)
+    assert abs(loss0 - 1.0) <= 1e-14
+    # a network whose bias alone is the exact correction (one element-independent
+    # correction: choose X so that it is)
+    c = 0.03 * rng.standard_normal(nst)
+    X2 = 2 * P - Pm + c[None, :]
+    parts = mlp.unflatten(zero.copy(), n_in, hidden, nst)
+    parts[5] = c / sD
+    loss1, _ = mlp.residual_loss_and_grad(mlp.flatten(parts), F, P, Pm, X2, S, hidden)
+    assert loss1 <= 1e-26
+    theta = _net(12, n_in, hidden, nst, scale=0.3)
+    loss, g = mlp.residual_loss_and_grad(theta, F, P, Pm, X, S, hidden)
+    h = 1e-6
+    fd = np.empty_like(theta)
+    for k in range(theta.size):
+        tp, tm = theta.copy(), theta.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd[k] = (mlp.residual_loss_and_grad(tp, F, P, Pm, X, S, hidden)[0]
+                 - mlp.residual_loss_and_grad(tm, F, P, Pm, X, S, hidden)[0]) / (2 * h)
+    assert np.abs(fd - g).max() <= 1e-6 * max(1.0, np.abs(g).max())
