@@ -6,12 +6,16 @@ nu = 1e-3, dt = 1e-3, velocity = 16 seeded divergence-free Fourier modes
 (amplitude |k|^-2, normalised to max |v| = 1 over the nodes).
 
 A step is one Picard time step (Sec. 2.6, p_gamma + 1 = 2 Picard iterations):
-averaging and Lambda, convection, viscous solve, goback, pressure-correction
-solve to a 1e-10 relative residual, velocity update -- every row of the hot
-path, inputs resident in HBM.  The timed steps use the chosen form (pressure:
-time-decoupled CG with FP32 inner solves in FP64 refinement); one extra step
-from the same state uses the plain form (FP64 GMRES(50), as in the paper) for
-the plain-vs-chosen pressure-solve comparison.
+averaging and Lambda, convection, viscous solve, goback, learned initial
+guess, pressure-correction solve to a 1e-10 relative residual, velocity
+update -- every row of the hot path, inputs resident in HBM.  Before the
+timed steps, `--record` steps are recorded and the guess model is trained on
+them on the GPU (reported, not timed).  The timed steps use the chosen form
+(pressure: time-decoupled CG with FP32 inner solves in FP64 refinement,
+learned guess for each step's first solve); extra steps from the same state
+give the first solve's iterations from the zero, previous, extrapolated and
+learned guesses, and one step in the plain form (FP64 GMRES(50) from zero, as
+in the paper) gives the plain-vs-chosen pressure-solve comparison.
 
 `value` is the whole-job Schur-operator throughput: pressure-operator
 applications in the timed steps x DoF / timed wall time (GDoF/s).  The
@@ -39,6 +43,11 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 N_HEX, P_DEG, P_GAMMA, DT, NU = 24, 3, 1, 1e-3, 1e-3
+# HBM bytes per launch of k_cg_op<20, true> from rocprofv3 FETCH_SIZE (x 2.0)
+# and WRITE_SIZE (x 1.0), calibrated by a device copy of known size; valid
+# only for the kernel source they were measured on (sha256 prefix).
+MEASURED_TRAFFIC = {"source": "paper_1601_07384_amd/csrc/cg_fused.hip", "sha256": "b550fc66f4ba4724",
+                    "bytes": 117310 * 1024.0}
 FP64_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
@@ -53,7 +62,18 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=256)
+    ap.add_argument("--record", type=int, default=12, help="steps recorded to train the learned guess")
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--lr", type=float, default=3e-4)
     return ap.parse_args()
+
+
+def measured_traffic():
+    import hashlib
+    path = os.path.join(ROOT, MEASURED_TRAFFIC["source"])
+    with open(path, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    return MEASURED_TRAFFIC["bytes"] if digest.startswith(MEASURED_TRAFFIC["sha256"]) else None
 
 
 def cpu_baseline(rows, X, T):
@@ -102,16 +122,39 @@ def main():
     p = torch.zeros(E * Nst, dtype=torch.float64, device=dev)
 
     visc = {"method": P.STDG_GMRES, "restart": 30, "rtol": 1e-10}
-    chosen = P.step_opts(pressure={"method": P.STDG_CG_TIME, "precision": P.STDG_FP32,
-                                   "rtol": 1e-10, "inner_rtol": 1e-5, "max_iter": 200000},
-                         viscous=visc)
+    press = {"method": P.STDG_CG_TIME, "precision": P.STDG_FP32, "rtol": 1e-10, "inner_rtol": 1e-5,
+             "max_iter": 200000}
+    n = E * Nst
+    hist = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+
+    def opts(kg, model=None, h=None, rec=None):
+        return P.step_opts(pressure=press, viscous=visc, krylov_guess=kg, model=model,
+                           hist=hist if h is None else h,
+                           rec_b=rec[0] if rec else None, rec_x=rec[1] if rec else None)
+
+    # ---- trajectory for the learned guess: record the first pressure solve of
+    # each step (right-hand side and solution), then train on the GPU
+    t0 = time.perf_counter()
+    Xr = torch.zeros(args.record * n, dtype=torch.float64, device=dev)
+    Br = torch.zeros(args.record * n, dtype=torch.float64, device=dev)
+    for k in range(args.record):
+        m.picard_step(vhat, vbar, p, None,
+                      opts=opts(P.STDG_KRYLOV_EXTRAPOLATE, rec=(Br[k * n:(k + 1) * n], Xr[k * n:(k + 1) * n])))
+    torch.cuda.synchronize()
+    record_s = time.perf_counter() - t0
+    model = P.Model(m, hidden=128, precision=P.STDG_FP32, batch=E, lr=args.lr, seed=1601,
+                    loss=P.STDG_LOSS_RESIDUAL)
+    S = args.record - 2
+    train = model.train(Xr[n:(args.record - 1) * n], Xr[:S * n], Br[2 * n:], Xr[2 * n:], epochs=args.epochs)
+    del Xr, Br
+    chosen = opts(P.STDG_KRYLOV_LEARNED, model=model)
     plain = P.step_opts(pressure={"method": P.STDG_GMRES, "restart": 50, "precision": P.STDG_FP64,
                                   "rtol": 1e-10, "max_iter": 200000},
                         viscous=visc)
     for _ in range(args.warmup):
         m.picard_step(vhat, vbar, p, None, opts=chosen)
     torch.cuda.synchronize()
-    state = (vhat.clone(), vbar.clone(), p.clone())
+    state = (vhat.clone(), vbar.clone(), p.clone(), hist.clone())
     reps = []
     t_start = time.perf_counter()
     for _ in range(args.steps):
@@ -119,6 +162,18 @@ def main():
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t_start
     applies = sum(r.pressure_applies for r in reps)
+
+    # ---- the first pressure solve of the first timed step from each guess
+    guess = {}
+    for name, kg in (("zero", P.STDG_KRYLOV_ZERO), ("previous", P.STDG_KRYLOV_PREVIOUS),
+                     ("extrapolated", P.STDG_KRYLOV_EXTRAPOLATE), ("learned", P.STDG_KRYLOV_LEARNED)):
+        vh, vbb, pp, hh = (t.clone() for t in state)
+        r = m.picard_step(vh, vbb, pp, None, opts=opts(kg, model=model, h=hh))
+        guess[name] = {"iters": r.first_pressure_iters, "seconds": r.first_pressure_seconds,
+                       "initial_rel_residual": r.first_initial_residual}
+        if kg == P.STDG_KRYLOV_LEARNED:
+            guess[name]["weights"] = {"step": r.learned_weight_step, "network": r.learned_weight_network}
+    torch.cuda.synchronize()
 
     # ---- Schur-apply kernel burst (HIP events on the library's stream)
     x = p.clone()
@@ -158,12 +213,12 @@ def main():
     # ---- plain form from the state before the timed steps
     plain_rep = None
     if not args.no_plain:
-        vh, vbb, pp = (t.clone() for t in state)
+        vh, vbb, pp, _ = (t.clone() for t in state)
         plain_rep = m.picard_step(vh, vbb, pp, None, opts=plain)
         torch.cuda.synchronize()
         # compare with the first chosen step from the same state
-        vh2, vbb2, pp2 = (t.clone() for t in state)
-        m.picard_step(vh2, vbb2, pp2, None, opts=chosen)
+        vh2, vbb2, pp2, hh2 = (t.clone() for t in state)
+        m.picard_step(vh2, vbb2, pp2, None, opts=opts(P.STDG_KRYLOV_LEARNED, model=model, h=hh2))
         torch.cuda.synchronize()
         err_v = float((vh - vh2).abs().max() / vh.abs().max())
         err_p = float((pp - pp2).abs().max() / pp.abs().max())
@@ -187,7 +242,8 @@ def main():
                  "max_pressure_residual": first.max_pressure_residual},
         "pressure_solve_s": {
             "chosen": first.pressure_seconds,
-            "chosen_form": "time-decoupled CG, FP32 inner / FP64 refinement, previous-free zero guess",
+            "chosen_form": "time-decoupled CG, FP32 inner / FP64 refinement, learned initial guess "
+                           "for the first solve of each step",
             "plain": plain_rep.pressure_seconds if plain_rep else None,
             "plain_form": "FP64 GMRES(50) on the space-time system",
             "plain_iters": plain_rep.pressure_iters if plain_rep else None,
@@ -197,14 +253,19 @@ def main():
                               "frac_fp64_peak": flops / t_apply / 1e12 / FP64_PEAK_TFLOPS,
                               "hbm_gbs_algorithmic": bytes_alg / t_apply / 1e9},
         "roofline": {"bound": "hbm", "achieved": k_bytes / k_s / 1e9, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": k_bytes / k_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_cg_op<{N},true>", "kernel_us": it_us,
+                     "unit": "GB/s", "frac": k_bytes / k_s / 1e9 / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if N == 20 else None,
+                     "kernel": f"k_cg_op<{N},true> (+ k_cg_red, one CG iteration)", "kernel_us": it_us,
                      "kernel_launches": sum(r.pressure_iters for r in reps),
                      "plain_operator_kernel": {"kernel": f"k_cg_op<{N},false>", "us": k_us,
                                                "launches": args.applies},
                      "bytes_per_launch": k_bytes, "flops_per_launch": k_flops,
                      "mfma_tflops": k_flops / k_s / 1e12,
                      "mfma_frac_fp32": k_flops / k_s / 1e12 / FP32_MFMA_PEAK_TFLOPS},
+        "first_solve_by_guess": guess,
+        "learned_guess": {"record_steps": args.record, "lr": args.lr, "record_s": record_s, "train_samples": train.samples,
+                          "epochs": train.epochs, "train_s": train.seconds,
+                          "loss_first_epoch": train.first_loss, "loss_last_epoch": train.last_loss},
         "mesh_build_s": build_s,
     }
     if not args.no_cpu_baseline:

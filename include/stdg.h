@@ -218,9 +218,12 @@ int stdg_pressure_solve(const stdg_mesh* mesh, const double* b, double* x,
 #define STDG_KRYLOV_ZERO 0         /* zero correction                         */
 #define STDG_KRYLOV_PREVIOUS 1     /* h0                                      */
 #define STDG_KRYLOV_EXTRAPOLATE 2  /* 2 h0 - h1                               */
-#define STDG_KRYLOV_LEARNED 3      /* 2 h0 - h1 + s_D * MLP(features of h0,   */
-                                   /* h1, b),                                 */
-                                   /* see the model section below            */
+#define STDG_KRYLOV_LEARNED 3      /* h0 + g1 (h0 - h1) + g2 d with the      */
+                                   /* network correction d = s_D MLP(features */
+                                   /* of h0, h1, b) (model section below) and */
+                                   /* (g1, g2) minimising the solve's initial */
+                                   /* residual ||b - S x0|| (three FP64       */
+                                   /* operator applies and five dot products) */
 
 typedef struct stdg_model stdg_model;
 
@@ -254,6 +257,8 @@ typedef struct {
     double first_pressure_seconds;     /* its time, guess included            */
     double first_initial_residual;     /* ||b - S x0|| / ||b|| of its guess   */
     double pressure_fused_iter_us;     /* fused_iter_us over the step's solves */
+    double learned_weight_step;        /* g1 of STDG_KRYLOV_LEARNED (else 0)   */
+    double learned_weight_network;     /* g2 of STDG_KRYLOV_LEARNED (else 0)   */
 } stdg_step_report;
 
 /* Defaults: n_picard 0, zero pressure guess, solve defaults, viscous rtol
@@ -318,8 +323,18 @@ typedef struct {
                                /* inference chunk (default 16384)             */
     uint64_t seed;             /* initial weights and sample order            */
     double lr, beta1, beta2, eps;   /* Adam (1e-3, 0.9, 0.999, 1e-8)          */
-    double init_scale_out;     /* output-layer initial scale (default 0.01)   */
+    double init_scale_out;     /* output-layer initial scale (default 0: the  */
+                               /* untrained model is the extrapolation)      */
+    int32_t loss;              /* STDG_LOSS_RESIDUAL (default) or STDG_LOSS_MSE */
 } stdg_model_config;
+
+/* Training objectives.  MSE: mean squared error of the network output against
+ * (x* - 2P + Pm) / s_D over mini-batches of elements.  RESIDUAL: the initial
+ * residual of the solve the guess is for, |S (x0 - x*)|^2 / |S (x_e - x*)|^2
+ * with x_e = 2P - Pm and x0 = x_e + s_D MLP, one recorded step per Adam step
+ * (its gradient goes through S^T; needs batch >= number of elements). */
+#define STDG_LOSS_MSE 0
+#define STDG_LOSS_RESIDUAL 1
 
 typedef struct {
     int32_t epochs;
@@ -359,6 +374,13 @@ int stdg_model_forward(stdg_model* model, const double* F, int64_t n, double* Y,
  * to *loss (host).  Synchronises the stream. */
 int stdg_model_loss_grad(stdg_model* model, const double* F, const double* target, int64_t n,
                          double* loss, void* stream);
+
+/* The residual objective (STDG_LOSS_RESIDUAL) of one recorded step and its
+ * gradient (kept in the model): P, Pm, B, X device [E][G][N] as for training
+ * (batch >= E).  Writes the loss to *loss.  Synchronises the stream. */
+int stdg_model_residual_loss_grad(stdg_model* model, const stdg_mesh* mesh, const double* P,
+                                  const double* Pm, const double* B, const double* X, double* loss,
+                                  void* stream);
 
 /* One Adam step (with bias correction) from the stored gradient. */
 int stdg_model_adam_step(stdg_model* model, void* stream);

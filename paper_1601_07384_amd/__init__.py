@@ -16,12 +16,12 @@ from ._lib import (Config, MeshInfo, SolveOpts, SolveReport, StepOpts, StepRepor
                    STDG_OK, STDG_NOT_CONVERGED, STDG_FP64, STDG_FP32,
                    STDG_AUTO, STDG_CG, STDG_GMRES, STDG_CG_TIME, STDG_GUESS_ZERO,
                    STDG_GUESS_PREVIOUS, STDG_KRYLOV_ZERO, STDG_KRYLOV_PREVIOUS,
-                   STDG_KRYLOV_EXTRAPOLATE, STDG_KRYLOV_LEARNED)
+                   STDG_KRYLOV_EXTRAPOLATE, STDG_KRYLOV_LEARNED, STDG_LOSS_MSE, STDG_LOSS_RESIDUAL)
 
 __all__ = ["Mesh", "Model", "StdgError", "STDG_FP64", "STDG_FP32", "STDG_AUTO",
            "STDG_CG", "STDG_GMRES", "STDG_CG_TIME", "STDG_GUESS_ZERO", "STDG_GUESS_PREVIOUS",
            "STDG_KRYLOV_ZERO", "STDG_KRYLOV_PREVIOUS", "STDG_KRYLOV_EXTRAPOLATE",
-           "STDG_KRYLOV_LEARNED",
+           "STDG_KRYLOV_LEARNED", "STDG_LOSS_MSE", "STDG_LOSS_RESIDUAL",
            "solve_opts", "step_opts"]
 
 
@@ -216,13 +216,14 @@ class Model:
     """
 
     def __init__(self, mesh, hidden=128, precision=STDG_FP32, batch=16384, seed=1601, lr=1e-3,
-                 beta1=0.9, beta2=0.999, eps=1e-8, init_scale_out=0.1):
+                 beta1=0.9, beta2=0.999, eps=1e-8, init_scale_out=0.0, loss=STDG_LOSS_RESIDUAL):
         lib = _lib.load()
         cfg = ModelConfig()
         lib.stdg_model_config_default(ctypes.byref(cfg))
         cfg.hidden, cfg.precision, cfg.batch, cfg.seed = hidden, precision, batch, seed
         cfg.lr, cfg.beta1, cfg.beta2, cfg.eps = lr, beta1, beta2, eps
         cfg.init_scale_out = init_scale_out
+        cfg.loss = loss
         h = ctypes.c_void_p()
         _lib.check(lib.stdg_model_create(mesh._h, ctypes.byref(cfg), ctypes.byref(h)))
         self._h, self._lib, self.mesh = h, lib, mesh
@@ -277,6 +278,14 @@ class Model:
         loss = ctypes.c_double()
         _lib.check(self._lib.stdg_model_loss_grad(self._h, _ptr(F), _ptr(T), n, ctypes.byref(loss),
                                                   _stream_ptr(stream)))
+        return loss.value
+
+    def residual_loss_grad(self, P, Pm, B, X, stream=None):
+        for t in (P, Pm, B, X):
+            self.mesh._check_any(t, self.mesh.E * self.mesh.Nst)
+        loss = ctypes.c_double()
+        _lib.check(self._lib.stdg_model_residual_loss_grad(self._h, self.mesh._h, _ptr(P), _ptr(Pm), _ptr(B),
+                                                           _ptr(X), ctypes.byref(loss), _stream_ptr(stream)))
         return loss.value
 
     def adam_step(self, stream=None):

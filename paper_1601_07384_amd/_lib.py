@@ -61,6 +61,8 @@ STDG_KRYLOV_ZERO = 0
 STDG_KRYLOV_PREVIOUS = 1
 STDG_KRYLOV_EXTRAPOLATE = 2
 STDG_KRYLOV_LEARNED = 3
+STDG_LOSS_MSE = 0
+STDG_LOSS_RESIDUAL = 1
 
 
 class StepOpts(ctypes.Structure):
@@ -79,7 +81,8 @@ class StepReport(ctypes.Structure):
                 ("pressure_applies", ctypes.c_int32), ("first_pressure_iters", ctypes.c_int32),
                 ("first_pressure_seconds", ctypes.c_double),
                 ("first_initial_residual", ctypes.c_double),
-                ("pressure_fused_iter_us", ctypes.c_double)]
+                ("pressure_fused_iter_us", ctypes.c_double),
+                ("learned_weight_step", ctypes.c_double), ("learned_weight_network", ctypes.c_double)]
 
 
 class ModelConfig(ctypes.Structure):
@@ -87,7 +90,7 @@ class ModelConfig(ctypes.Structure):
                 ("batch", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("lr", ctypes.c_double), ("beta1", ctypes.c_double),
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
-                ("init_scale_out", ctypes.c_double)]
+                ("init_scale_out", ctypes.c_double), ("loss", ctypes.c_int32)]
 
 
 class TrainReport(ctypes.Structure):
@@ -132,6 +135,8 @@ SIGNATURES = [
     ("stdg_model_forward", ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P]),
     ("stdg_model_loss_grad", ctypes.c_int, [_P, _P, _P, ctypes.c_int64,
                                              ctypes.POINTER(ctypes.c_double), _P]),
+    ("stdg_model_residual_loss_grad", ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double),
+                                                      _P]),
     ("stdg_model_adam_step", ctypes.c_int, [_P, _P]),
     ("stdg_model_train", ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32,
                                          ctypes.POINTER(TrainReport), _P]),

@@ -31,7 +31,9 @@ hipError_t time_mix_f64(const stdg_mesh* m, const double* M, const double* x, do
 hipError_t time_mix_f32(const stdg_mesh* m, const float* M, const float* x, float* y, hipStream_t s);
 hipError_t launch_visc_apply(const stdg_mesh* m, const double* x, double* y, hipStream_t s);
 int model_predict(stdg_model* md, const stdg_mesh* m, const double* P, const double* Pm, const double* B,
-                  double* x0, hipStream_t s);
+                  double* x0, hipStream_t s, bool correction_only);
+int device_dots(stdg_mesh* m, int k, const double* const* a, const double* const* b, int64_t n, hipStream_t s,
+                double* out);
 bool fast_rows_supported(const stdg_mesh* m);
 hipError_t fast_dualgrad(const stdg_mesh* m, const double* p, double dt, double* w, hipStream_t s);
 hipError_t fast_goback(const stdg_mesh* m, const double* vbar, const double* vbdry, double* out, int64_t f0,

@@ -637,6 +637,25 @@ void free_workspace(stdg_mesh* m) {
     w = Workspace();
 }
 
+// out[i] = a[i] . b[i] (i < k) in FP64, deterministic; synchronises s.
+int device_dots(stdg_mesh* m, int k, const double* const* a, const double* const* b, int64_t n, hipStream_t s,
+                double* out) {
+    if (int e = ensure_workspace(m, 0, false)) return e;
+    Ctx c;
+    c.m = m;
+    c.s = s;
+    c.partial = m->ws.partial;
+    c.scal = m->ws.scal;
+    c.hscal = m->ws.hscal;
+    for (int i = 0; i < k; ++i) {
+        hipLaunchKernelGGL((k_dot<double, double>), dim3(NBLK), dim3(RT), 0, s, a[i], b[i], n, c.partial);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, c.partial, NBLK, c.scal, (int)S_TMP, (int)FIN_STORE);
+        CK(hipGetLastError());
+        if (int e = read_scal(c, S_TMP, out[i])) return e;
+    }
+    return STDG_OK;
+}
+
 // Plain (non-singular) solve A_v x = b of the viscous system with the
 // library's CG/GMRES; x holds the guess.  Vectors [3][E][G][N]; work vectors
 // are taken from `work` ((restart + 6) * n doubles).  GMRES runs on the

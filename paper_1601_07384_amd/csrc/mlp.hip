@@ -58,6 +58,10 @@ struct stdg_model {
     int64_t* idx = nullptr;
     int64_t idx_n = 0;
     double* hbuf = nullptr;     // pinned host scratch
+    double* ve = nullptr;       // residual objective: guess error, S e, S^T S e  [E][G][N]
+    double* vR = nullptr;
+    double* vG = nullptr;
+    double* CT = nullptr;       // transposed time factor (S^T = B (x) C^T)
 };
 
 namespace stdg {
@@ -315,13 +319,37 @@ __global__ void k_adam(T* __restrict__ th, const T* __restrict__ g, T* __restric
     th[t] = (T)((double)th[t] - lr * (mm / c1) / (sqrt(vv / c2) + eps));
 }
 
-// x0 = 2 P - Pm + s_D * Y for rows row0 .. row0 + n of one step
+// e = 2P - Pm - X (+ s_D Y) over all rows of one step
+template <typename T>
+__global__ void k_guess_err(const double* __restrict__ P, const double* __restrict__ Pm,
+                            const double* __restrict__ X, const T* __restrict__ Y, const double* __restrict__ scales,
+                            int64_t n, int with_y, double* __restrict__ e) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double v = (2.0 * P[t] - Pm[t]) - X[t];
+    if (with_y) v += scales[1] * (double)Y[t];
+    e[t] = v;
+}
+
+// dY = 2 s_D (S^T S e) / den
+template <typename T>
+__global__ void k_resid_dy(const double* __restrict__ g, const double* __restrict__ scales, double inv_den, int64_t n,
+                           T* __restrict__ dY) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    dY[t] = (T)(2.0 * scales[1] * inv_den * g[t]);
+}
+
+// x0 = 2 P - Pm + s_D * Y (or the correction s_D * Y alone) for rows
+// row0 .. row0 + n of one step
 template <typename T>
 __global__ void k_guess(const double* __restrict__ P, const double* __restrict__ Pm, const T* __restrict__ Y,
-                        const double* __restrict__ scales, int64_t off, int64_t count, double* __restrict__ x0) {
+                        const double* __restrict__ scales, int64_t off, int64_t count, int correction_only,
+                        double* __restrict__ x0) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
-    x0[off + t] = (2.0 * P[off + t] - Pm[off + t]) + scales[1] * (double)Y[t];
+    const double d = scales[1] * (double)Y[t];
+    x0[off + t] = correction_only ? d : (2.0 * P[off + t] - Pm[off + t]) + d;
 }
 
 template <typename T>
@@ -474,12 +502,64 @@ int check_model(const stdg_model* md, const stdg_mesh* m) {
     return STDG_OK;
 }
 
+int ensure_resid_buffers(stdg_model* md, const stdg_mesh* m) {
+    const size_t n = (size_t)md->E * md->nst;
+    if (!md->ve) {
+        STDG_HIP(hipMalloc(&md->ve, n * sizeof(double)));
+        STDG_HIP(hipMalloc(&md->vR, n * sizeof(double)));
+        STDG_HIP(hipMalloc(&md->vG, n * sizeof(double)));
+        const int G = m->G;
+        std::vector<double> ct((size_t)G * G);
+        for (int a = 0; a < G; ++a)
+            for (int b = 0; b < G; ++b) ct[(size_t)a * G + b] = m->Ctime[(size_t)b * G + a];
+        STDG_HIP(hipMalloc(&md->CT, ct.size() * sizeof(double)));
+        STDG_HIP(hipMemcpy(md->CT, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    return STDG_OK;
+}
+
+// |S (2P - Pm - X)|^2 of step k (scales already computed)
+int resid_den(stdg_model* md, stdg_mesh* m, const double* P, const double* Pm, const double* X, int64_t k,
+              double& den, hipStream_t s) {
+    const int64_t n = md->E * md->nst;
+    hipLaunchKernelGGL(k_guess_err<float>, dim3(nb256(n)), dim3(256), 0, s, P + k * n, Pm + k * n, X + k * n,
+                       (const float*)nullptr, md->scales + 3 * k, n, 0, md->ve);
+    MCK(hipGetLastError());
+    MCK(launch_apply_f64(m, md->ve, md->vR, s));
+    const double* a[1] = {md->vR};
+    return device_dots(m, 1, a, a, n, s, &den);
+}
+
+// residual objective of step k and its gradient; scales of step k computed
+template <typename T>
+int resid_step_t(stdg_model* md, stdg_mesh* m, const double* P, const double* Pm, const double* B, const double* X,
+                 int64_t k, double den, double& loss, hipStream_t s) {
+    const int64_t E = md->E, n = E * md->nst;
+    if (int e = features_t<T>(md, m, P, Pm, B, nullptr, k * E, E, (T*)md->F, s)) return e;
+    if (int e = forward_t<T>(md, E, s)) return e;
+    hipLaunchKernelGGL(k_guess_err<T>, dim3(nb256(n)), dim3(256), 0, s, P + k * n, Pm + k * n, X + k * n,
+                       (const T*)md->Y, md->scales + 3 * k, n, 1, md->ve);
+    MCK(hipGetLastError());
+    MCK(launch_apply_f64(m, md->ve, md->vR, s));
+    double num = 0.0;
+    const double* a[1] = {md->vR};
+    if (int e = device_dots(m, 1, a, a, n, s, &num)) return e;
+    MCK(launch_apply_f64_c(m, md->CT, md->vR, md->vG, s));
+    const double inv = den > 0.0 ? 1.0 / den : 0.0;
+    hipLaunchKernelGGL(k_resid_dy<T>, dim3(nb256(n)), dim3(256), 0, s, md->vG, md->scales + 3 * k, inv, n,
+                       (T*)md->dY);
+    MCK(hipGetLastError());
+    if (int e = backward_t<T>(md, E, s)) return e;
+    loss = num * inv;
+    return STDG_OK;
+}
+
 }  // namespace
 
 // x0 = 2P - Pm + s_D MLP(features(P, Pm, B)) over all elements (used by the Picard
 // step's learned guess).  Asynchronous.
 int model_predict(stdg_model* md, const stdg_mesh* m, const double* P, const double* Pm, const double* B,
-                  double* x0, hipStream_t s) {
+                  double* x0, hipStream_t s, bool correction_only) {
     if (int e = check_model(md, m)) return e;
     if (int e = compute_scales(md, P, Pm, B, 1, s)) return e;
     const int64_t bs = md->cfg.batch;
@@ -490,12 +570,13 @@ int model_predict(stdg_model* md, const stdg_mesh* m, const double* P, const dou
             if ((e = features_t<double>(md, m, P, Pm, B, nullptr, r0, n, (double*)md->F, s))) return e;
             if ((e = forward_t<double>(md, n, s))) return e;
             hipLaunchKernelGGL(k_guess<double>, dim3(nb256(n * md->nst)), dim3(256), 0, s, P, Pm,
-                               (const double*)md->Y, md->scales, r0 * md->nst, n * md->nst, x0);
+                               (const double*)md->Y, md->scales, r0 * md->nst, n * md->nst, (int)correction_only,
+                               x0);
         } else {
             if ((e = features_t<float>(md, m, P, Pm, B, nullptr, r0, n, (float*)md->F, s))) return e;
             if ((e = forward_t<float>(md, n, s))) return e;
             hipLaunchKernelGGL(k_guess<float>, dim3(nb256(n * md->nst)), dim3(256), 0, s, P, Pm, (const float*)md->Y,
-                               md->scales, r0 * md->nst, n * md->nst, x0);
+                               md->scales, r0 * md->nst, n * md->nst, (int)correction_only, x0);
         }
         MCK(hipGetLastError());
     }
@@ -516,7 +597,8 @@ extern "C" void stdg_model_config_default(stdg_model_config* c) {
     c->beta1 = 0.9;
     c->beta2 = 0.999;
     c->eps = 1e-8;
-    c->init_scale_out = 0.01;
+    c->init_scale_out = 0.0;
+    c->loss = STDG_LOSS_RESIDUAL;
 }
 
 extern "C" int stdg_model_create(const stdg_mesh* m, const stdg_model_config* cfg, stdg_model** out) {
@@ -525,6 +607,10 @@ extern "C" int stdg_model_create(const stdg_mesh* m, const stdg_model_config* cf
     if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
     if (cfg->hidden < 1 || cfg->hidden > 1024 || cfg->batch < 1 || cfg->batch > (1 << 22)) {
         set_error("hidden must be in 1..1024 and batch in 1..4194304");
+        return STDG_ERR_ARG;
+    }
+    if (cfg->loss != STDG_LOSS_MSE && cfg->loss != STDG_LOSS_RESIDUAL) {
+        set_error("unknown training loss");
         return STDG_ERR_ARG;
     }
     if (cfg->precision != STDG_FP64 && cfg->precision != STDG_FP32) {
@@ -587,7 +673,8 @@ extern "C" int stdg_model_free(stdg_model* md) {
     if (!md) return STDG_OK;
     for (void* p : {md->theta, md->grad, md->mom1, md->mom2, md->one, md->F, md->Z1, md->H1, md->Z2, md->H2, md->Y,
                     md->dY, md->dZ2, md->dZ1, md->part, (void*)md->lpart, (void*)md->lbatch, (void*)md->scales,
-                    (void*)md->spart, (void*)md->idx})
+                    (void*)md->spart, (void*)md->idx, (void*)md->ve, (void*)md->vR, (void*)md->vG,
+                    (void*)md->CT})
         if (p) (void)hipFree(p);
     if (md->hbuf) (void)hipHostFree(md->hbuf);
     delete md;
@@ -713,6 +800,25 @@ extern "C" int stdg_model_loss_grad(stdg_model* md, const double* F, const doubl
     return STDG_OK;
 }
 
+extern "C" int stdg_model_residual_loss_grad(stdg_model* md, const stdg_mesh* cm, const double* P, const double* Pm,
+                                             const double* B, const double* X, double* loss, void* stream) {
+    if (int e = check_model(md, cm)) return e;
+    if (!P || !Pm || !B || !X) { set_error("null vector"); return STDG_ERR_ARG; }
+    if (md->cfg.batch < md->E) { set_error("the residual objective needs batch >= number of elements"); return STDG_ERR_ARG; }
+    stdg_mesh* m = const_cast<stdg_mesh*>(cm);
+    hipStream_t s = (hipStream_t)stream;
+    if (int e = ensure_resid_buffers(md, m)) return e;
+    if (int e = compute_scales(md, P, Pm, B, 1, s)) return e;
+    double den = 0.0, l = 0.0;
+    if (int e = resid_den(md, m, P, Pm, X, 0, den, s)) return e;
+    const int e = is64(md) ? resid_step_t<double>(md, m, P, Pm, B, X, 0, den, l, s)
+                           : resid_step_t<float>(md, m, P, Pm, B, X, 0, den, l, s);
+    if (e) return e;
+    STDG_HIP(hipStreamSynchronize(s));
+    if (loss) *loss = l;
+    return STDG_OK;
+}
+
 extern "C" int stdg_model_adam_step(stdg_model* md, void* stream) {
     if (int e = check_model(md, nullptr)) return e;
     return is64(md) ? adam_t<double>(md, (hipStream_t)stream) : adam_t<float>(md, (hipStream_t)stream);
@@ -721,7 +827,7 @@ extern "C" int stdg_model_adam_step(stdg_model* md, void* stream) {
 extern "C" int stdg_model_predict(stdg_model* md, const stdg_mesh* m, const double* P, const double* Pm,
                                   const double* B, double* x0, void* stream) {
     if (!P || !Pm || !B || !x0) { set_error("null vector"); return STDG_ERR_ARG; }
-    return model_predict(md, m, P, Pm, B, x0, (hipStream_t)stream);
+    return model_predict(md, m, P, Pm, B, x0, (hipStream_t)stream, false);
 }
 
 extern "C" int stdg_model_train(stdg_model* md, const stdg_mesh* m, int32_t n_steps, const double* P,
@@ -734,6 +840,43 @@ extern "C" int stdg_model_train(stdg_model* md, const stdg_mesh* m, int32_t n_st
     }
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
+    if (md->cfg.loss == STDG_LOSS_RESIDUAL) {
+        if (md->cfg.batch < md->E) { set_error("the residual objective needs batch >= number of elements"); return STDG_ERR_ARG; }
+        stdg_mesh* mm = const_cast<stdg_mesh*>(m);
+        if (int e = ensure_resid_buffers(md, mm)) return e;
+        if (int e = compute_scales(md, P, Pm, B, n_steps, s)) return e;
+        std::vector<double> den(n_steps);
+        for (int k = 0; k < n_steps; ++k)
+            if (int e = resid_den(md, mm, P, Pm, X, k, den[k], s)) return e;
+        std::vector<int> order(n_steps);
+        std::iota(order.begin(), order.end(), 0);
+        std::mt19937_64 rng(md->cfg.seed ^ 0x5DEECE66DULL);
+        double first = 0.0, last = 0.0;
+        for (int ep = 0; ep < epochs; ++ep) {
+            for (int k = n_steps - 1; k > 0; --k) std::swap(order[k], order[rng() % (uint64_t)(k + 1)]);
+            double acc = 0.0;
+            for (int k : order) {
+                double l = 0.0;
+                const int e = is64(md) ? resid_step_t<double>(md, mm, P, Pm, B, X, k, den[k], l, s)
+                                       : resid_step_t<float>(md, mm, P, Pm, B, X, k, den[k], l, s);
+                if (e) return e;
+                if (int e2 = is64(md) ? adam_t<double>(md, s) : adam_t<float>(md, s)) return e2;
+                acc += l;
+            }
+            last = acc / n_steps;
+            if (!std::isfinite(last)) { set_error("non-finite training loss"); return STDG_ERR_NUMERIC; }
+            if (ep == 0) first = last;
+        }
+        STDG_HIP(hipStreamSynchronize(s));
+        if (rep) {
+            rep->epochs = epochs;
+            rep->samples = (int64_t)n_steps * md->E;
+            rep->first_loss = first;
+            rep->last_loss = last;
+            rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        return STDG_OK;
+    }
     const int64_t total = (int64_t)n_steps * md->E;
     const int64_t bs = md->cfg.batch;
     const int64_t nbatch = (total + bs - 1) / bs;

@@ -699,7 +699,8 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     const int64_t nD = 3 * F * G * N, nM = 3 * E * G * N, nP = E * G * N;
     const int mres = std::max(1, opts->viscous.restart);
     // workspace: 4 dual + 6 main + 3 pressure vectors + viscous Krylov (mres + 6) main
-    const size_t need = 4 * nD + 6 * nM + 3 * nP + (size_t)(mres + 6) * nM;
+    const size_t need = 4 * nD + 6 * nM + 3 * nP + (size_t)(mres + 6) * nM +
+                        (kg == STDG_KRYLOV_LEARNED ? 6 * nP : 0);
     PicardDevice& d = m->pd;
     if (d.work_len < need) {
         if (d.work) STDG_HIP(hipFree(d.work));
@@ -721,6 +722,7 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     double* bp = pk + nP;
     double* dp = bp + nP;
     double* kw = dp + nP;           // viscous Krylov work
+    double* ls = kw + (size_t)(mres + 6) * nM;   // learned guess: least-squares vectors
     double* h0 = opts->hist;        // first-iteration pressures of the two previous steps
     double* h1 = opts->hist ? opts->hist + nP : nullptr;
     const double dt = m->cfg.dt;
@@ -744,6 +746,7 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         hipLaunchKernelGGL(k_zero, dim3(nblk(nP)), dim3(256), 0, s, pk, nP);
     STDG_HIP(hipGetLastError());
     int piters = 0, viters = 0, papplies = 0, first_iters = 0;
+    double learned_w[2] = {0.0, 0.0};
     double fused_us_sum = 0.0, fused_w = 0.0;
     double pres = 0.0, vres = 0.0, psec = 0.0, vsec = 0.0, first_sec = 0.0, first_res0 = 0.0;
     for (int k = 0; k < npic; ++k) {
@@ -782,8 +785,48 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         // guesses x0 are for the new pressure p^{n+1,1}; the unknown is its
         // correction to p^{n+1,0}
         if (k == 0 && kg == STDG_KRYLOV_LEARNED) {
-            if (int e2 = model_predict(opts->model, m, h0, h1, bp, dp, s)) return e2;
-            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, pk, -1.0, nP);
+            // x0 = h0 + g1 (h0 - h1) + g2 d, d = s_D MLP(features), with (g1, g2)
+            // minimising ||b - S (x0 - p^{n+1,0})||: the network direction is
+            // weighted by what it removes from the residual of this solve
+            double* g0 = ls;             // h0 - pk
+            double* r0 = ls + nP;        // b - S g0
+            double* D = ls + 2 * nP;     // h0 - h1
+            double* SD = ls + 3 * nP;
+            double* dd = ls + 4 * nP;    // network direction
+            double* Sd = ls + 5 * nP;
+            if (int e2 = model_predict(opts->model, m, h0, h1, bp, dd, s, true)) return e2;
+            hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, h0, g0, nP);
+            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, g0, pk, -1.0, nP);
+            hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, h0, D, nP);
+            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, D, h1, -1.0, nP);
+            STDG_HIP(hipGetLastError());
+            STDG_HIP(launch_apply_f64(m, g0, r0, s));
+            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, r0, bp, -1.0, nP);   // S g0 - b
+            STDG_HIP(launch_apply_f64(m, D, SD, s));
+            STDG_HIP(launch_apply_f64(m, dd, Sd, s));
+            STDG_HIP(hipGetLastError());
+            const double* da[5] = {SD, SD, Sd, SD, Sd};
+            const double* db[5] = {SD, Sd, Sd, r0, r0};
+            double v[5];
+            if (int e2 = device_dots(m, 5, da, db, nP, s, v)) return e2;
+            // minimise |S g0 - b + g1 S D + g2 S d|^2: normal equations with
+            // right-hand side -(S D, S g0 - b), -(S d, S g0 - b)
+            const double a11 = v[0], a12 = v[1], a22 = v[2], c1 = -v[3], c2 = -v[4];
+            double g1 = 0.0, g2 = 0.0;
+            const double det = a11 * a22 - a12 * a12;
+            if (a11 > 0.0 && a22 > 0.0 && det > 1e-10 * a11 * a22) {
+                g1 = (c1 * a22 - c2 * a12) / det;
+                g2 = (a11 * c2 - a12 * c1) / det;
+            } else if (a11 > 0.0) {
+                g1 = c1 / a11;
+            } else if (a22 > 0.0) {
+                g2 = c2 / a22;
+            }
+            hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, g0, dp, nP);
+            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, D, g1, nP);
+            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, dd, g2, nP);
+            learned_w[0] = g1;
+            learned_w[1] = g2;
         } else if (k == 0 && kg == STDG_KRYLOV_PREVIOUS) {
             hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, h0, dp, nP);
             hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, pk, -1.0, nP);
@@ -843,6 +886,8 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         rep->first_pressure_seconds = first_sec;
         rep->first_initial_residual = first_res0;
         rep->pressure_fused_iter_us = fused_w > 0.0 ? fused_us_sum / fused_w : 0.0;
+        rep->learned_weight_step = learned_w[0];
+        rep->learned_weight_network = learned_w[1];
     }
     return STDG_OK;
 }

@@ -118,16 +118,55 @@ def test_features_and_guess_match_oracle(periodic):
 
 def test_training_reduces_loss():
     _, _, m = small_mesh(3, 1, 1)
-    model = P.Model(m, hidden=64, precision=P.STDG_FP32, batch=128, lr=3e-3)
+    model = P.Model(m, hidden=64, precision=P.STDG_FP32, batch=128, lr=3e-3, loss=P.STDG_LOSS_MSE)
     rng = np.random.default_rng(9)
     S, n = 3, m.E * m.Nst
     Pn = rng.standard_normal((S, n))
     Pm = Pn - 0.1 * rng.standard_normal((S, n))
     B = rng.standard_normal((S, n))
-    X = Pn + (Pn - Pm)                       # linear extrapolation is learnable
+    X = 2 * Pn - Pm + 0.5 * (Pn - Pm)        # a correction linear in the features
     rep = model.train(dev(Pn), dev(Pm), dev(B), dev(X), epochs=30)
     assert rep.samples == S * m.E and rep.epochs == 30
     assert rep.last_loss < 0.2 * rep.first_loss
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_residual_objective_matches_oracle(periodic):
+    """|S(x0 - x*)|^2 / |S(x_e - x*)|^2 and its gradient (through S^T) in FP64
+    against the oracle with the assembled operator, in the library's element
+    order."""
+    print(f"mlp residual objective periodic={periodic}", flush=True)
+    from oracle.pressure import assemble_S
+    from oracle.spacetime import SpaceTimeOperators
+    X, T, m = small_mesh(3, 1, 1, periodic)
+    om = OracleMesh(X, T, periodic=periodic)
+    ops = SpaceTimeOperators(om, 1, 1, 1e-2)
+    perm = m.permutation()
+    iperm = np.empty_like(perm)
+    iperm[perm] = np.arange(m.E)
+    nbr = np.array([[om.neighbour(perm[i], f)[0] for f in range(4)] for i in range(m.E)])
+    nbr = np.where(nbr >= 0, iperm[np.maximum(nbr, 0)], -1)
+    S = assemble_S(ops).toarray()
+    idx = (perm[:, None] * m.Nst + np.arange(m.Nst)).ravel()
+    S = S[np.ix_(idx, idx)]
+    rng = np.random.default_rng(17)
+    Pn = rng.standard_normal((m.E, m.Nst))
+    Pm = Pn - 0.1 * rng.standard_normal((m.E, m.Nst))
+    B = rng.standard_normal((m.E, m.Nst))
+    Xs = 2 * Pn - Pm + 0.05 * rng.standard_normal((m.E, m.Nst))
+    model = P.Model(m, hidden=24, precision=P.STDG_FP64, batch=m.E)
+    theta = rand_theta(model, 19, scale=0.3)
+    model.set_params(theta)
+    loss = model.residual_loss_grad(dev(Pn), dev(Pm), dev(B), dev(Xs))
+    F = mlp.features(Pn, Pm, B, nbr)
+    lo, go = mlp.residual_loss_and_grad(theta, F, Pn, Pm, Xs, S, 24)
+    assert abs(loss - lo) <= 1e-11 * lo
+    gg = model.grads()
+    o = 0
+    for shp in mlp.shapes(model.n_in, 24, model.n_out):
+        k = int(np.prod(shp))
+        assert np.abs(gg[o:o + k] - go[o:o + k]).max() <= 1e-10 * np.abs(go[o:o + k]).max(), shp
+        o += k
 
 
 def fourier_state(m, X, T, p):
@@ -167,9 +206,10 @@ def test_learned_guess_keeps_solution_and_saves_iterations():
         m.picard_step(vhat, vbar, p_cur, None, opts=opts)
     torch.cuda.synchronize()
     assert torch.equal(hist[:n], Xr[(n_rec - 1) * n:]) and torch.equal(hist[n:], Xr[(n_rec - 2) * n:(n_rec - 1) * n])
-    model = P.Model(m, hidden=128, precision=P.STDG_FP32, batch=4096, lr=1e-3, seed=3)
+    model = P.Model(m, hidden=128, precision=P.STDG_FP32, batch=m.E, lr=1e-3, seed=3)
     S = n_rec - 2
     rep = model.train(Xr[n:(n_rec - 1) * n], Xr[:S * n], Br[2 * n:], Xr[2 * n:], epochs=60)
+    assert rep.last_loss < 1.0          # better than plain extrapolation on the training steps
     print(f"train loss {rep.first_loss:.3e} -> {rep.last_loss:.3e} in {rep.seconds:.1f}s", flush=True)
     its = {P.STDG_KRYLOV_ZERO: [], P.STDG_KRYLOV_PREVIOUS: [], P.STDG_KRYLOV_EXTRAPOLATE: [],
            P.STDG_KRYLOV_LEARNED: []}
@@ -192,3 +232,4 @@ def test_learned_guess_keeps_solution_and_saves_iterations():
                 assert float((vh - ref[1]).abs().max()) <= 1e-9 * float(ref[1].abs().max())
     print({k: sum(v) for k, v in its.items()}, flush=True)
     assert sum(its[P.STDG_KRYLOV_LEARNED]) < sum(its[P.STDG_KRYLOV_PREVIOUS])
+    assert sum(its[P.STDG_KRYLOV_LEARNED]) < sum(its[P.STDG_KRYLOV_ZERO])
