@@ -125,7 +125,7 @@ def main():
     press = {"method": P.STDG_CG_TIME, "precision": P.STDG_FP32, "rtol": 1e-10, "inner_rtol": 1e-5,
              "max_iter": 200000}
     n = E * Nst
-    hist = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+    hist = torch.zeros(2 * G * n, dtype=torch.float64, device=dev)     # 2 steps x p_gamma + 1 solves
 
     def opts(kg, model=None, h=None, rec=None):
         return P.step_opts(pressure=press, viscous=visc, krylov_guess=kg, model=model,
@@ -171,8 +171,9 @@ def main():
         r = m.picard_step(vh, vbb, pp, None, opts=opts(kg, model=model, h=hh))
         guess[name] = {"iters": r.first_pressure_iters, "seconds": r.first_pressure_seconds,
                        "initial_rel_residual": r.first_initial_residual}
+        guess[name]["step_pressure_iters"] = r.pressure_iters
         if kg == P.STDG_KRYLOV_LEARNED:
-            guess[name]["weights"] = {"step": r.learned_weight_step, "network": r.learned_weight_network}
+            guess[name]["network_weight"] = r.guess_weight_network
     torch.cuda.synchronize()
 
     # ---- Schur-apply kernel burst (HIP events on the library's stream)

@@ -210,20 +210,21 @@ int stdg_pressure_solve(const stdg_mesh* mesh, const double* b, double* x,
 #define STDG_GUESS_ZERO 0       /* p^{n+1,0} = 0 (the paper's choice)        */
 #define STDG_GUESS_PREVIOUS 1   /* p^{n+1,0} = previous slab's pressure      */
 
-/* Krylov initial guess of the first pressure-correction solve of a step.
- * That solve yields the first Picard pressure p^{n+1,1} (its unknown is the
- * correction to p^{n+1,0}); the guesses below predict p^{n+1,1} from the same
- * quantity of the two previous steps, h0 = p^{n,1} and h1 = p^{n-1,1}, kept
- * by the caller in `hist`.  Later Picard iterations start from zero.        */
+/* Krylov start of the pressure-correction solves (eq. A2_mod) of Picard
+ * iteration k, from the same solve of the two previous steps kept by the
+ * caller in `hist`: h0_k, h1_k = that solve's value one and two steps back
+ * (for k = 0 the new pressure p^{n+1,1}, whose unknown is its correction to
+ * p^{n+1,0}; for k >= 1 the correction itself).                            */
 #define STDG_KRYLOV_ZERO 0         /* zero correction                         */
-#define STDG_KRYLOV_PREVIOUS 1     /* h0                                      */
-#define STDG_KRYLOV_EXTRAPOLATE 2  /* 2 h0 - h1                               */
-#define STDG_KRYLOV_LEARNED 3      /* h0 + g1 (h0 - h1) + g2 d with the      */
-                                   /* network correction d = s_D MLP(features */
-                                   /* of h0, h1, b) (model section below) and */
-                                   /* (g1, g2) minimising the solve's initial */
-                                   /* residual ||b - S x0|| (three FP64       */
-                                   /* operator applies and five dot products) */
+#define STDG_KRYLOV_PREVIOUS 1     /* h0_k                                    */
+#define STDG_KRYLOV_EXTRAPOLATE 2  /* 2 h0_k - h1_k                           */
+#define STDG_KRYLOV_LEARNED 3      /* k = 0: 2 h0 - h1 + g d with the network */
+                                   /* correction d = s_D MLP(features of h0,  */
+                                   /* h1, b) (model section below) and g      */
+                                   /* minimising the solve's initial residual */
+                                   /* ||b - S x0|| (two FP64 operator applies */
+                                   /* and two dot products; g = 0 is the      */
+                                   /* extrapolation); k >= 1: 2 h0_k - h1_k   */
 
 typedef struct stdg_model stdg_model;
 
@@ -234,10 +235,11 @@ typedef struct {
     stdg_solve_opts viscous;    /* viscous solves (eq. A1_mod), FP64 only    */
     int32_t krylov_guess;       /* STDG_KRYLOV_*                              */
     stdg_model* model;          /* STDG_KRYLOV_LEARNED: the trained model     */
-    double* hist;               /* device [2][E][G][N] or NULL (needed by all */
-                                /* guesses but ZERO): on entry (h0, h1), on   */
-                                /* exit (p^{n+1,1}, h0); zeros before the     */
-                                /* first step                                 */
+    double* hist;               /* device [n_pic][2][E][G][N] or NULL (needed */
+                                /* by all guesses but ZERO): per Picard       */
+                                /* iteration k, (h0_k, h1_k) on entry, this   */
+                                /* step's value and h0_k on exit; zeros       */
+                                /* before the first step                      */
     double* rec_b;              /* device [E][G][N] or NULL: receives the     */
                                 /* right-hand side of the first pressure solve */
     double* rec_x;              /* device [E][G][N] or NULL: receives         */
@@ -257,8 +259,7 @@ typedef struct {
     double first_pressure_seconds;     /* its time, guess included            */
     double first_initial_residual;     /* ||b - S x0|| / ||b|| of its guess   */
     double pressure_fused_iter_us;     /* fused_iter_us over the step's solves */
-    double learned_weight_step;        /* g1 of STDG_KRYLOV_LEARNED (else 0)   */
-    double learned_weight_network;     /* g2 of STDG_KRYLOV_LEARNED (else 0)   */
+    double guess_weight_network;       /* g of STDG_KRYLOV_LEARNED (else 0)    */
 } stdg_step_report;
 
 /* Defaults: n_picard 0, zero pressure guess, solve defaults, viscous rtol

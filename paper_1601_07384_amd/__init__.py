@@ -165,7 +165,8 @@ class Mesh:
             self._check_any(g_nodal, 3 * self.E * self.Nst)
         o = opts if opts is not None else step_opts(**kw)
         keep = getattr(o, "_keep", (None, None, None, None))
-        for t, n in zip(keep[1:], (2, 1, 1)):
+        n_pic = o.n_picard if o.n_picard > 0 else self.G
+        for t, n in zip(keep[1:], (2 * n_pic, 1, 1)):
             if t is not None:
                 self._check_any(t, n * self.E * self.Nst)
         rep = StepReport()

@@ -700,7 +700,8 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     const int mres = std::max(1, opts->viscous.restart);
     // workspace: 4 dual + 6 main + 3 pressure vectors + viscous Krylov (mres + 6) main
     const size_t need = 4 * nD + 6 * nM + 3 * nP + (size_t)(mres + 6) * nM +
-                        (kg == STDG_KRYLOV_LEARNED ? 6 * nP : 0);
+                        (kg == STDG_KRYLOV_LEARNED ? 4 * nP : 0);   // learned-start vectors
+    const bool zero_base = opts->pressure_guess == STDG_GUESS_ZERO;
     PicardDevice& d = m->pd;
     if (d.work_len < need) {
         if (d.work) STDG_HIP(hipFree(d.work));
@@ -723,16 +724,45 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     double* dp = bp + nP;
     double* kw = dp + nP;           // viscous Krylov work
     double* ls = kw + (size_t)(mres + 6) * nM;   // learned guess: least-squares vectors
-    double* h0 = opts->hist;        // first-iteration pressures of the two previous steps
-    double* h1 = opts->hist ? opts->hist + nP : nullptr;
+    // history per Picard iteration k (two previous steps): slot 2k holds the
+    // last step's value, slot 2k + 1 the one before; the value is the new
+    // pressure p^{n+1,1} for k = 0 and the correction for k >= 1
+    auto hist_at = [&](int k, int which) -> double* {
+        return opts->hist ? opts->hist + (size_t)(2 * k + which) * nP : nullptr;
+    };
+    // learned start of the first solve: x0 = x_e + g d with the extrapolation
+    // x_e = 2 h0 - h1, the network correction d, and g minimising
+    // ||b + S base - S x0|| (g = 0 gives x_e back); returned as x0 - base
+    auto learned_guess = [&](const double* h0, const double* h1, const double* d, double* out,
+                             double& g) -> int {
+        double* xe = ls;
+        double* rb = ls + nP;
+        double* Sd = ls + 2 * nP;
+        hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, h0, xe, nP);
+        hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, xe, h0, 1.0, nP);
+        hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, xe, h1, -1.0, nP);
+        if (!zero_base) hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, xe, pk, -1.0, nP);
+        STDG_HIP(hipGetLastError());
+        STDG_HIP(launch_apply_f64(m, xe, rb, s));                     // S (x_e - base)
+        hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, rb, bp, -1.0, nP);   // S (x_e - base) - b
+        STDG_HIP(launch_apply_f64(m, d, Sd, s));
+        STDG_HIP(hipGetLastError());
+        const double* da[2] = {Sd, Sd};
+        const double* db[2] = {Sd, rb};
+        double v[2];
+        if (int e2 = device_dots(m, 2, da, db, nP, s, v)) return e2;
+        g = v[0] > 0.0 ? -v[1] / v[0] : 0.0;
+        hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, xe, out, nP);
+        if (g != 0.0) hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, out, d, g, nP);
+        STDG_HIP(hipGetLastError());
+        return STDG_OK;
+    };
     const double dt = m->cfg.dt;
     // step 0
     hipLaunchKernelGGL(k_copyd, dim3(nblk(nM)), dim3(256), 0, s, vbar, vprev, nM);
     hipLaunchKernelGGL(k_time_end, dim3(nblk(3 * F * N)), dim3(256), 0, s, vhat, vk, d.g1, 3 * F, G, N);
     hipLaunchKernelGGL(k_zero, dim3(nblk(nD)), dim3(256), 0, s, vbc, nD);
     if (F > NI) {
-        const int64_t nb = 3 * (F - NI) * G * N;
-        (void)nb;
         STDG_HIP(run_goback(m, g_nodal, g_nodal, vbc, NI, F, s));
         // boundary part of the iterate = prescribed data
         for (int c = 0; c < 3; ++c)
@@ -746,7 +776,7 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         hipLaunchKernelGGL(k_zero, dim3(nblk(nP)), dim3(256), 0, s, pk, nP);
     STDG_HIP(hipGetLastError());
     int piters = 0, viters = 0, papplies = 0, first_iters = 0;
-    double learned_w[2] = {0.0, 0.0};
+    double guess_w = 0.0;
     double fused_us_sum = 0.0, fused_w = 0.0;
     double pres = 0.0, vres = 0.0, psec = 0.0, vsec = 0.0, first_sec = 0.0, first_res0 = 0.0;
     for (int k = 0; k < npic; ++k) {
@@ -782,59 +812,23 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         const auto tg0 = std::chrono::steady_clock::now();
         if (k == 0 && opts->rec_b)
             hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, bp, opts->rec_b, nP);
-        // guesses x0 are for the new pressure p^{n+1,1}; the unknown is its
-        // correction to p^{n+1,0}
-        if (k == 0 && kg == STDG_KRYLOV_LEARNED) {
-            // x0 = h0 + g1 (h0 - h1) + g2 d, d = s_D MLP(features), with (g1, g2)
-            // minimising ||b - S (x0 - p^{n+1,0})||: the network direction is
-            // weighted by what it removes from the residual of this solve
-            double* g0 = ls;             // h0 - pk
-            double* r0 = ls + nP;        // b - S g0
-            double* D = ls + 2 * nP;     // h0 - h1
-            double* SD = ls + 3 * nP;
-            double* dd = ls + 4 * nP;    // network direction
-            double* Sd = ls + 5 * nP;
+        // Krylov start of solve k from that solve's history (k = 0: the new
+        // pressure p^{n+1,1}, whose unknown is its correction to p^{n+1,0})
+        double* h0 = hist_at(k, 0);
+        double* h1 = hist_at(k, 1);
+        const double* base = (k == 0 && !zero_base) ? pk : nullptr;
+        if (kg == STDG_KRYLOV_LEARNED && k == 0) {
+            double* dd = ls + 3 * nP;
             if (int e2 = model_predict(opts->model, m, h0, h1, bp, dd, s, true)) return e2;
-            hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, h0, g0, nP);
-            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, g0, pk, -1.0, nP);
-            hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, h0, D, nP);
-            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, D, h1, -1.0, nP);
-            STDG_HIP(hipGetLastError());
-            STDG_HIP(launch_apply_f64(m, g0, r0, s));
-            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, r0, bp, -1.0, nP);   // S g0 - b
-            STDG_HIP(launch_apply_f64(m, D, SD, s));
-            STDG_HIP(launch_apply_f64(m, dd, Sd, s));
-            STDG_HIP(hipGetLastError());
-            const double* da[5] = {SD, SD, Sd, SD, Sd};
-            const double* db[5] = {SD, Sd, Sd, r0, r0};
-            double v[5];
-            if (int e2 = device_dots(m, 5, da, db, nP, s, v)) return e2;
-            // minimise |S g0 - b + g1 S D + g2 S d|^2: normal equations with
-            // right-hand side -(S D, S g0 - b), -(S d, S g0 - b)
-            const double a11 = v[0], a12 = v[1], a22 = v[2], c1 = -v[3], c2 = -v[4];
-            double g1 = 0.0, g2 = 0.0;
-            const double det = a11 * a22 - a12 * a12;
-            if (a11 > 0.0 && a22 > 0.0 && det > 1e-10 * a11 * a22) {
-                g1 = (c1 * a22 - c2 * a12) / det;
-                g2 = (a11 * c2 - a12 * c1) / det;
-            } else if (a11 > 0.0) {
-                g1 = c1 / a11;
-            } else if (a22 > 0.0) {
-                g2 = c2 / a22;
-            }
-            hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, g0, dp, nP);
-            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, D, g1, nP);
-            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, dd, g2, nP);
-            learned_w[0] = g1;
-            learned_w[1] = g2;
-        } else if (k == 0 && kg == STDG_KRYLOV_PREVIOUS) {
+            if (int e2 = learned_guess(h0, h1, dd, dp, guess_w)) return e2;
+        } else if (kg == STDG_KRYLOV_PREVIOUS) {
             hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, h0, dp, nP);
-            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, pk, -1.0, nP);
-        } else if (k == 0 && kg == STDG_KRYLOV_EXTRAPOLATE) {
+            if (base) hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, base, -1.0, nP);
+        } else if (kg == STDG_KRYLOV_EXTRAPOLATE || kg == STDG_KRYLOV_LEARNED) {
             hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, h0, dp, nP);
             hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, h0, 1.0, nP);
             hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, h1, -1.0, nP);
-            hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, pk, -1.0, nP);
+            if (base) hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, dp, base, -1.0, nP);
         } else {
             hipLaunchKernelGGL(k_zero, dim3(nblk(nP)), dim3(256), 0, s, dp, nP);
         }
@@ -859,13 +853,13 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         STDG_HIP(run_dualgrad(m, dp, dt, wg, s));
         hipLaunchKernelGGL(k_update, dim3(nblk(nD)), dim3(256), 0, s, Fv, wg, vk, F, NI, G, N);
         hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, pk, dp, 1.0, nP);
-        if (k == 0) {
-            // pk = p^{n+1,1}: record it and push it into the history
-            if (opts->rec_x) hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, pk, opts->rec_x, nP);
-            if (h0) {
-                hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, h0, h1, nP);
-                hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, pk, h0, nP);
-            }
+        if (k == 0 && opts->rec_x)      // pk = p^{n+1,1}
+            hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, pk, opts->rec_x, nP);
+        if (opts->hist) {
+            // push this solve's value into its history
+            double* h0 = hist_at(k, 0);
+            hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, h0, hist_at(k, 1), nP);
+            hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, k == 0 ? pk : dp, h0, nP);
         }
         STDG_HIP(hipGetLastError());
     }
@@ -886,8 +880,7 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         rep->first_pressure_seconds = first_sec;
         rep->first_initial_residual = first_res0;
         rep->pressure_fused_iter_us = fused_w > 0.0 ? fused_us_sum / fused_w : 0.0;
-        rep->learned_weight_step = learned_w[0];
-        rep->learned_weight_network = learned_w[1];
+        rep->guess_weight_network = guess_w;
     }
     return STDG_OK;
 }

@@ -193,7 +193,7 @@ def test_learned_guess_keeps_solution_and_saves_iterations():
     vhat, vbar = fourier_state(m, X, T, p)
     n = m.E * m.Nst
     p_cur = torch.zeros(n, dtype=torch.float64, device=DEV)
-    hist = torch.zeros(2 * n, dtype=torch.float64, device=DEV)
+    hist = torch.zeros(2 * m.G * n, dtype=torch.float64, device=DEV)     # 2 steps x 2 Picard solves
     solve = {"method": P.STDG_CG_TIME, "precision": P.STDG_FP32, "rtol": 1e-10, "inner_rtol": 1e-5,
              "max_iter": 100000}
     visc = {"method": P.STDG_GMRES, "restart": 30, "rtol": 1e-10}
@@ -205,7 +205,7 @@ def test_learned_guess_keeps_solution_and_saves_iterations():
                            rec_b=Br[k * n:(k + 1) * n], rec_x=Xr[k * n:(k + 1) * n])
         m.picard_step(vhat, vbar, p_cur, None, opts=opts)
     torch.cuda.synchronize()
-    assert torch.equal(hist[:n], Xr[(n_rec - 1) * n:]) and torch.equal(hist[n:], Xr[(n_rec - 2) * n:(n_rec - 1) * n])
+    assert torch.equal(hist[:n], Xr[(n_rec - 1) * n:]) and torch.equal(hist[n:2 * n], Xr[(n_rec - 2) * n:(n_rec - 1) * n])
     model = P.Model(m, hidden=128, precision=P.STDG_FP32, batch=m.E, lr=1e-3, seed=3)
     S = n_rec - 2
     rep = model.train(Xr[n:(n_rec - 1) * n], Xr[:S * n], Br[2 * n:], Xr[2 * n:], epochs=60)
@@ -213,6 +213,7 @@ def test_learned_guess_keeps_solution_and_saves_iterations():
     print(f"train loss {rep.first_loss:.3e} -> {rep.last_loss:.3e} in {rep.seconds:.1f}s", flush=True)
     its = {P.STDG_KRYLOV_ZERO: [], P.STDG_KRYLOV_PREVIOUS: [], P.STDG_KRYLOV_EXTRAPOLATE: [],
            P.STDG_KRYLOV_LEARNED: []}
+    steps_its = {k: [] for k in its}
     for step in range(n_eval):
         state = [t.clone() for t in (vhat, vbar, p_cur, hist)]
         ref = None
@@ -223,13 +224,14 @@ def test_learned_guess_keeps_solution_and_saves_iterations():
                                                model=model if kg == P.STDG_KRYLOV_LEARNED else None))
             torch.cuda.synchronize()
             its[kg].append(r.first_pressure_iters)
-            print(f"eval step {step} guess {kg}: {r.first_pressure_iters} it, r0 {r.first_initial_residual:.2e}",
-                  flush=True)
+            steps_its[kg].append(r.pressure_iters)
+            print(f"eval step {step} guess {kg}: first solve {r.first_pressure_iters} it, r0 "
+                  f"{r.first_initial_residual:.2e}; step {r.pressure_iters} it", flush=True)
             if ref is None:
                 ref = (pc.clone(), vh.clone())
             else:
                 assert float((pc - ref[0]).abs().max()) <= 1e-8 * float(ref[0].abs().max())
                 assert float((vh - ref[1]).abs().max()) <= 1e-9 * float(ref[1].abs().max())
-    print({k: sum(v) for k, v in its.items()}, flush=True)
+    print({k: sum(v) for k, v in its.items()}, {k: sum(v) for k, v in steps_its.items()}, flush=True)
     assert sum(its[P.STDG_KRYLOV_LEARNED]) < sum(its[P.STDG_KRYLOV_PREVIOUS])
     assert sum(its[P.STDG_KRYLOV_LEARNED]) < sum(its[P.STDG_KRYLOV_ZERO])
