@@ -93,6 +93,11 @@ def cpu_baseline(rows, X, T):
                       f"matrices integrated per face, extended precision), {t:.1f} s"}
 
 
+def progress(msg):
+    """One line per finished phase on stderr (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -106,6 +111,7 @@ def main():
     t0 = time.perf_counter()
     m = P.Mesh(X, T, P_DEG, P_GAMMA, dt=DT, nu=NU, periodic=True)
     build_s = time.perf_counter() - t0
+    progress(f"mesh built: {build_s:.1f} s")
     perm = m.permutation()
     E, G, N, Nst = m.E, m.G, m.N, m.Nst
     dev = torch.device("cuda:0")
@@ -142,11 +148,13 @@ def main():
                       opts=opts(P.STDG_KRYLOV_EXTRAPOLATE, rec=(Br[k * n:(k + 1) * n], Xr[k * n:(k + 1) * n])))
     torch.cuda.synchronize()
     record_s = time.perf_counter() - t0
+    progress(f"recorded {args.record} steps: {record_s:.1f} s")
     model = P.Model(m, hidden=128, precision=P.STDG_FP32, batch=E, lr=args.lr, seed=1601,
                     loss=P.STDG_LOSS_RESIDUAL)
     S = args.record - 2
     train = model.train(Xr[n:(args.record - 1) * n], Xr[:S * n], Br[2 * n:], Xr[2 * n:], epochs=args.epochs)
     del Xr, Br
+    progress(f"guess model trained: {train.seconds:.1f} s")
     chosen = opts(P.STDG_KRYLOV_LEARNED, model=model)
     plain = P.step_opts(pressure={"method": P.STDG_GMRES, "restart": 50, "precision": P.STDG_FP64,
                                   "rtol": 1e-10, "max_iter": 200000},
@@ -162,6 +170,7 @@ def main():
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t_start
     applies = sum(r.pressure_applies for r in reps)
+    progress(f"timed steps: {t_steps / args.steps * 1e3:.1f} ms per step")
 
     # ---- the first pressure solve of the first timed step from each guess
     guess = {}
@@ -176,6 +185,7 @@ def main():
             guess[name]["network_weight"] = r.guess_weight_network
     torch.cuda.synchronize()
 
+    progress("first solves by guess done")
     # ---- Schur-apply kernel burst (HIP events on the library's stream)
     x = p.clone()
     y = torch.empty_like(x)
@@ -211,6 +221,7 @@ def main():
     k_flops = 2.0 * N * N * 5 * E * G
     k_s = it_us * 1e-6 if it_us > 0 else float("nan")
 
+    progress("kernel bursts done")
     # ---- plain form from the state before the timed steps
     plain_rep = None
     if not args.no_plain:
@@ -223,6 +234,7 @@ def main():
         torch.cuda.synchronize()
         err_v = float((vh - vh2).abs().max() / vh.abs().max())
         err_p = float((pp - pp2).abs().max() / pp.abs().max())
+        progress(f"plain FP64 GMRES step: {plain_rep.pressure_seconds:.1f} s in the pressure solve")
 
     first = reps[0]
     out = {
@@ -270,6 +282,7 @@ def main():
         "mesh_build_s": build_s,
     }
     if not args.no_cpu_baseline:
+        progress("oracle sample on the host")
         out["cpu_baseline"] = cpu_baseline(args.cpu_rows, X, T)
     print(json.dumps(out))
 

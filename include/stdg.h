@@ -148,6 +148,9 @@ int stdg_pressure_apply(const stdg_mesh* mesh, int32_t precision,
 int stdg_pressure_apply_f32(const stdg_mesh* mesh, const float* x, float* y,
                             void* stream);
 
+#define STDG_PRECOND_NONE 0
+#define STDG_PRECOND_BLOCK_JACOBI 1
+
 typedef struct {
     int32_t method;        /* STDG_AUTO, STDG_CG, STDG_GMRES or STDG_CG_TIME  */
     int32_t restart;       /* GMRES restart length m (1..200)                  */
@@ -158,6 +161,13 @@ typedef struct {
     double inner_rtol;     /* relative tolerance of each inner solve (FP32)    */
     int32_t max_outer;     /* refinement steps allowed (FP32)                  */
     int32_t check_every;   /* host polls convergence every k iterations (>=1)  */
+    int32_t precond;       /* STDG_PRECOND_BLOCK_JACOBI (the default) or       */
+                           /* STDG_PRECOND_NONE: preconditioner M of the FP32  */
+                           /* CG inner solves on B (x) I (method STDG_CG_TIME, */
+                           /* or STDG_CG at p_gamma = 0) for p = 1, 2, 3: M is  */
+                           /* each element's own diagonal block of B (its      */
+                           /* class's, inverted once per class), used when     */
+                           /* every such block is SPD; other solves ignore it */
 } stdg_solve_opts;
 
 typedef struct {

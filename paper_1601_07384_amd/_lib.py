@@ -45,7 +45,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("precond", ctypes.c_int32)]
 
 
 class SolveReport(ctypes.Structure):
@@ -57,6 +58,8 @@ class SolveReport(ctypes.Structure):
 
 STDG_GUESS_ZERO = 0
 STDG_GUESS_PREVIOUS = 1
+STDG_PRECOND_NONE = 0
+STDG_PRECOND_BLOCK_JACOBI = 1
 STDG_KRYLOV_ZERO = 0
 STDG_KRYLOV_PREVIOUS = 1
 STDG_KRYLOV_EXTRAPOLATE = 2

@@ -59,11 +59,11 @@ int upload_tables(stdg_mesh* m) {
         STDG_HIP(hipMemcpy(m->d.Cid, cid.data(), G * G * sizeof(double), hipMemcpyHostToDevice));
         STDG_HIP(hipMemcpy(m->d.Cid32, cid32.data(), G * G * sizeof(float), hipMemcpyHostToDevice));
     }
-    return STDG_OK;
+    return upload_cg_operands(m);
 }
 
 void free_tables(stdg_mesh* m) {
-    for (void* p : {(void*)m->d.blocks, (void*)m->d.blocks32, (void*)m->d.cls, (void*)m->d.nbr,
+    for (void* p : {(void*)m->d.blocks, (void*)m->d.blocks32, (void*)m->d.aop32, (void*)m->d.cls, (void*)m->d.nbr,
                     (void*)m->d.C, (void*)m->d.C32, (void*)m->d.Cinv, (void*)m->d.Cinv32,
                     (void*)m->d.Cid, (void*)m->d.Cid32})
         if (p) (void)hipFree(p);

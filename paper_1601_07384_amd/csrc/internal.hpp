@@ -33,6 +33,8 @@ struct Face {
 struct DeviceTables {
     double* blocks = nullptr;     // [n_classes][5][N][N]  dt^2 S^sp blocks
     float* blocks32 = nullptr;    // same, FP32
+    float* aop32 = nullptr;       // FP32 blocks per lane in MFMA operand order (fused CG kernel)
+    int cg_precond_ok = 0;        // every own block SPD: block-Jacobi operands in aop32
     int32_t* cls = nullptr;       // [E]
     int32_t* nbr = nullptr;       // [E][4]  -1 on a boundary face
     double* C = nullptr;          // [G][G]  time factor W T^-1 W

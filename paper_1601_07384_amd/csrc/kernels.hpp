@@ -19,12 +19,15 @@ hipError_t launch_apply_f64_c(const stdg_mesh* m, const double* C, const double*
 hipError_t launch_apply_f32_c(const stdg_mesh* m, const float* C, const float* x, float* y, hipStream_t s);
 constexpr int CG_UPD_BLOCKS = 1024;
 bool cg_fused_supported(const stdg_mesh* m);
+int upload_cg_operands(stdg_mesh* m);
 int64_t cg_op_blocks(const stdg_mesh* m);
+int64_t cg_partial_len(const stdg_mesh* m);   // doubles of one launch's partials
 hipError_t launch_cg_iter_f32(const stdg_mesh* m, float* x, const float* r_in, const float* p_in, const float* q_in,
-                              float* r_out, float* p_out, float* q_out, int iter, float cscale,
+                              float* r_out, float* p_out, float* q_out, int iter, float cscale, bool precond,
                               const double* part_in, int64_t n_in, double* part_out, double* ab, hipStream_t s);
+hipError_t launch_cg_prec_f32(const stdg_mesh* m, const float* x, float* y, float scale, hipStream_t s);
 hipError_t launch_cg_apply_f32(const stdg_mesh* m, const float* x, float* y, float cscale, hipStream_t s);
-hipError_t launch_cg_tail_f32(float* x, const float* p, int64_t n, const double* part, int64_t n_part,
+hipError_t launch_cg_tail_f32(float* x, const float* p, int64_t n, const double* part, int64_t n_part, double* ab,
                               hipStream_t s);
 hipError_t launch_cg_check_f32(const double* part, int64_t n_part, double* scal, int slot, hipStream_t s);
 hipError_t time_mix_f64(const stdg_mesh* m, const double* M, const double* x, double* y, hipStream_t s);

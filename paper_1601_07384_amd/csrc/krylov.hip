@@ -147,9 +147,16 @@ __global__ void k_fill(T* __restrict__ v, T val, int64_t n) {
 }
 
 // x += (double) d
-__global__ void k_add_f32(double* __restrict__ x, const float* __restrict__ d, int64_t n) {
+// x += scale d
+__global__ void k_add_f32(double* __restrict__ x, const float* __restrict__ d, double scale, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        x[i] += (double)d[i];
+        x[i] += scale * (double)d[i];
+}
+
+// b = (float)(scale a)
+__global__ void k_d2f_scaled(const double* __restrict__ a, float* __restrict__ b, double scale, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)(scale * a[i]);
 }
 
 template <typename T>
@@ -336,6 +343,7 @@ struct Ctx {
     int op = 0;        // 0: pressure Schur operator, 1: viscous operator (3 components),
                        // 2: B (x) I, 3: block-Jacobi preconditioned viscous operator D^-1 A
     double* tmp = nullptr;   // op 3: holds A x before D^-1
+    bool precond = false;    // block-Jacobi preconditioning of the fused FP32 CG
     int applies = 0;
     double loop_ms = 0.0;    // device time of the one-kernel CG iterations (HIP events)
     int loop_iters = 0;
@@ -392,7 +400,7 @@ int time_sums(Ctx& c, const double* v) {
 bool cg_fusable(const Ctx& c) {
     const stdg_mesh* m = c.m;
     return (c.op == 2 || (c.op == 0 && m->G == 1)) && cg_fused_supported(m) && m->ws.p32b && m->ws.r32b &&
-           m->ws.q32b && 8 * cg_op_blocks(m) <= (int64_t)NBLK * 208;
+           m->ws.q32b && 2 * cg_partial_len(m) <= (int64_t)NBLK * 208;
 }
 
 int cg_fused(Ctx& c, const float* b, float* x, float* r, float* p, float* q, double tol_abs, int max_it,
@@ -404,12 +412,16 @@ int cg_fused(Ctx& c, const float* b, float* x, float* r, float* p, float* q, dou
     float* pb[2] = {p, m->ws.p32b};
     float* qb[2] = {q, m->ws.q32b};
     const int64_t nb = cg_op_blocks(m);
-    double* part[2] = {c.partial, c.partial + 4 * nb};
+    double* part[2] = {c.partial, c.partial + cg_partial_len(m)};
+    const bool precond = c.precond && m->d.cg_precond_ok;
     const float cscale = c.op == 2 ? 1.0f : (float)m->Ctime[0];
     // r_0 = b - A x, rr_0 into the even rr slot; p_{-1} = q_{-1} = 0
     CK(Apply<float>::run(c, x, qb[1])); c.applies++;
     hipLaunchKernelGGL((k_resid<float, float>), dim3(NBLK), dim3(RT), 0, c.s, b, qb[1], rb[0], n, c.partial);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_FRR, (int)FIN_STORE);
+    // the iteration carries z = M^-1 r and w = M^-1 q (M = c diag(B_e)) in
+    // the r and q buffers; p_{-1} = w_{-1} = 0
+    if (precond) CK(launch_cg_prec_f32(m, rb[0], rb[0], 1.0f / cscale, c.s));
     hipLaunchKernelGGL(k_fill<float>, dim3(gb), dim3(256), 0, c.s, pb[0], 0.0f, n);
     hipLaunchKernelGGL(k_fill<float>, dim3(gb), dim3(256), 0, c.s, qb[0], 0.0f, n);
     CK(hipGetLastError());
@@ -438,10 +450,15 @@ int cg_fused(Ctx& c, const float* b, float* x, float* r, float* p, float* q, dou
     };
     const hipEvent_t t0ev = m->ws.ev[2], t1ev = m->ws.ev[3];
     CK(hipEventRecord(t0ev, c.s));
-    while (iters < max_it && status != STDG_OK) {
+    // an iteration with alpha = 0 (p.q not positive: breakdown) changes
+    // nothing, so r.r repeating bit for bit between two checks means the
+    // iteration has stalled; the solve then stops, not converged
+    double last_rr = -1.0;
+    bool stalled = false;
+    while (iters < max_it && status != STDG_OK && !stalled) {
         const int i = iters, in = i & 1, out = in ^ 1;
-        CK(launch_cg_iter_f32(m, x, rb[in], pb[in], qb[in], rb[out], pb[out], qb[out], i, cscale, part[out], nb,
-                              part[in], c.scal + S_FRR, c.s));
+        CK(launch_cg_iter_f32(m, x, rb[in], pb[in], qb[in], rb[out], pb[out], qb[out], i, cscale, precond,
+                              part[out], nb, part[in], c.scal + S_FRR, c.s));
         c.applies++;
         ++iters;
         if (iters % check_every == 0 || iters == max_it) {
@@ -449,6 +466,8 @@ int cg_fused(Ctx& c, const float* b, float* x, float* r, float* p, float* q, dou
             if (pending >= 0) {
                 if (int e = read_check(slot ^ 1, rr)) return e;
                 if (std::sqrt(rr) <= tol_abs) status = STDG_OK;
+                else if (rr == last_rr) stalled = true;
+                last_rr = rr;
             }
             pending = iters;
             slot ^= 1;
@@ -457,7 +476,7 @@ int cg_fused(Ctx& c, const float* b, float* x, float* r, float* p, float* q, dou
     CK(hipEventRecord(t1ev, c.s));
     if (iters == 0) return STDG_NOT_CONVERGED;
     // x += alpha p of the last iteration, then the newest residual
-    CK(launch_cg_tail_f32(x, pb[iters & 1], n, part[(iters - 1) & 1], nb, c.s));
+    CK(launch_cg_tail_f32(x, pb[iters & 1], n, part[(iters - 1) & 1], nb, c.scal + S_FRR, c.s));
     {
         float ms = 0.0f;
         CK(hipEventSynchronize(t1ev));
@@ -746,6 +765,7 @@ extern "C" void stdg_solve_opts_default(stdg_solve_opts* o) {
     o->inner_rtol = 1e-4;
     o->max_outer = 30;
     o->check_every = 8;
+    o->precond = STDG_PRECOND_BLOCK_JACOBI;
 }
 
 extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double* x,
@@ -766,6 +786,7 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
     }
     if (o.method == STDG_GMRES && (o.restart < 1 || o.restart > 200)) { set_error("restart out of range"); return STDG_ERR_ARG; }
     if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1) { set_error("bad tolerance/iteration options"); return STDG_ERR_ARG; }
+    if (o.precond != STDG_PRECOND_NONE && o.precond != STDG_PRECOND_BLOCK_JACOBI) { set_error("bad preconditioner"); return STDG_ERR_ARG; }
     if (o.precision != STDG_FP64 && o.precision != STDG_FP32) { set_error("bad precision"); return STDG_ERR_ARG; }
     const bool ir = o.precision == STDG_FP32;
     if (ir && (!(o.inner_rtol > 0.0) || o.max_outer < 1)) { set_error("bad refinement options"); return STDG_ERR_ARG; }
@@ -780,6 +801,7 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
     c.scal = w.scal;
     c.hscal = w.hscal;
     c.gm = w.scal + S_COUNT;
+    c.precond = o.precond == STDG_PRECOND_BLOCK_JACOBI;
     const int64_t n = c.n;
     const int gb = grid_for(n);
     const int G = m->G, N = m->N;
@@ -849,10 +871,15 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
             hipLaunchKernelGGL(k_remove_mean<double>, dim3(gb), dim3(256), 0, c.s, w.r, c.scal + S_TIME, m->E, G, N);
             hipLaunchKernelGGL((k_dot<double, double>), dim3(NBLK), dim3(RT), 0, c.s, w.r, w.r, n, c.partial);
             hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_NORM, (int)FIN_SQRT);
-            CK(convert_d2f(w.r, w.b32, n, c.s));
-            hipLaunchKernelGGL(k_fill<float>, dim3(gb), dim3(256), 0, c.s, w.x32, 0.0f, n);
             double rn;
             if (int e = read_scal(c, S_NORM, rn)) return e;
+            if (!(rn > 0.0)) { status = STDG_NOT_CONVERGED; break; }
+            // the inner system is solved for the unit-norm right-hand side
+            // r / |r| (FP32 vectors and products then stay far from the ends
+            // of the FP32 range whatever the scale of the problem) and the
+            // correction scaled back by |r|
+            hipLaunchKernelGGL(k_d2f_scaled, dim3(gb), dim3(256), 0, c.s, w.r, w.b32, 1.0 / rn, n);
+            hipLaunchKernelGGL(k_fill<float>, dim3(gb), dim3(256), 0, c.s, w.x32, 0.0f, n);
             int it = 0;
             double res = 0.0;
             // each inner solve reduces the residual by inner_rtol, but never
@@ -860,10 +887,10 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
             // then saves inner iterations instead of overshooting)
             const double inner_abs = std::max(o.inner_rtol * rn, 0.25 * o.rtol * bnorm);
             status = run_krylov<float>(c, o.method, w.b32, w.x32, w.r32, w.p32, w.q32, w.V32, mres,
-                                       inner_abs, o.max_iter - inner_total, o.check_every, it, res);
+                                       inner_abs / rn, o.max_iter - inner_total, o.check_every, it, res);
             inner_total += it;
             if (status < 0) return status;
-            hipLaunchKernelGGL(k_add_f32, dim3(gb), dim3(256), 0, c.s, x, w.x32, n);
+            hipLaunchKernelGGL(k_add_f32, dim3(gb), dim3(256), 0, c.s, x, w.x32, rn, n);
             CK(hipGetLastError());
         }
         outer = std::min(outer, o.max_outer);
