@@ -322,22 +322,20 @@ __global__ void __launch_bounds__(256) k_cg_op(const float* __restrict__ A, cons
         bload<W>(rx, off[0], xo);
         if (REM > 0) bload<1>(rx, offr[0], &xo[W]);
     }
-    constexpr int NCOPY = (NT * 16 + 255) / 256;
-    f4 acopy[NCOPY];
     {
+        // straight from global memory into LDS, 64 float4 per wavefront and
+        // instruction (the table is a whole number of such pieces)
         const f4* src = A4 + (size_t)cb * NT * 16;
+        const int wu = __builtin_amdgcn_readfirstlane(wave);
 #pragma unroll
-        for (int j = 0; j < NCOPY; ++j) {
-            const int i = threadIdx.x + 256 * j;
-            acopy[j] = i < NT * 16 ? src[i] : f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int j = 0; j < (NT * 16 + 255) / 256; ++j) {
+            const int i0 = 256 * j + 64 * wu;
+            if (i0 < NT * 16)
+                __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(src + i0 + lane),
+                                                 (__attribute__((address_space(3))) void*)(As + i0), 16, 0, 0);
         }
     }
     __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int j = 0; j < NCOPY; ++j) {
-        const int i = threadIdx.x + 256 * j;
-        if (i < NT * 16) As[i] = acopy[j];
-    }
     __syncthreads();
     float aop[NA];
     ops_load<NA>(As, lane, 0, aop);
