@@ -12,7 +12,8 @@ update -- every row of the hot path, inputs resident in HBM.  Before the
 timed steps, `--record` steps are recorded and the guess model is trained on
 them on the GPU (reported, not timed).  The timed steps use the chosen form
 (pressure: time-decoupled CG with FP32 inner solves in FP64 refinement,
-learned guess for each step's first solve); extra steps from the same state
+block-Jacobi preconditioned, learned guess for each step's first solve;
+viscous: block-Jacobi preconditioned BiCGStab); extra steps from the same state
 give the first solve's iterations from the zero, previous, extrapolated and
 learned guesses, and one step in the plain form (FP64 GMRES(50) from zero, as
 in the paper) gives the plain-vs-chosen pressure-solve comparison.
@@ -20,12 +21,13 @@ in the paper) gives the plain-vs-chosen pressure-solve comparison.
 `value` is the whole-job Schur-operator throughput: pressure-operator
 applications in the timed steps x DoF / timed wall time (GDoF/s).  The
 roofline entry is for the step's dominant kernel, the one-kernel FP32 CG
-iteration k_cg_op<N, true> (r, p updates while staging the operand panels,
-q = (B (x) I) p on MFMA, x update, four dot-product partials).  Its duration
+iteration k_cg_op<N, true> (z = M^-1 r and p updates of the gathered rows,
+q = (B (x) I) p on MFMA, w = M^-1 q, r = M z and x on the own rows, five
+dot-product partials).  Its duration
 is the library's own HIP-event measurement on its stream around the
 back-to-back iteration launches of every inner solve of the timed steps
 (stdg_step_report.pressure_fused_iter_us).  Algorithmic bytes per launch:
-read r, p, q, x and write r, p, q, x once (8 x 4 B per DoF) plus 20 B of
+read z, p, w, x and write z, p, w, x once (8 x 4 B per DoF) plus 20 B of
 indices per element; flops: 2 N^2 x 5 blocks per column.  The plain FP32
 operator kernel (stdg_pressure_apply_spatial_f32) and the FP64 Schur apply
 are timed with HIP events over bursts of launches (context).
@@ -127,7 +129,7 @@ def main():
     m.dual_from_main(vbar, vhat)
     p = torch.zeros(E * Nst, dtype=torch.float64, device=dev)
 
-    visc = {"method": P.STDG_GMRES, "restart": 30, "rtol": 1e-10}
+    visc = {"method": P.STDG_BICGSTAB, "restart": 30, "rtol": 1e-10, "check_every": 1}
     press = {"method": P.STDG_CG_TIME, "precision": P.STDG_FP32, "rtol": 1e-10, "inner_rtol": 1e-5,
              "max_iter": 200000}
     n = E * Nst
@@ -255,8 +257,8 @@ def main():
                  "max_pressure_residual": first.max_pressure_residual},
         "pressure_solve_s": {
             "chosen": first.pressure_seconds,
-            "chosen_form": "time-decoupled CG, FP32 inner / FP64 refinement, learned initial guess "
-                           "for the first solve of each step",
+            "chosen_form": "time-decoupled CG, block-Jacobi preconditioned, FP32 inner / FP64 "
+                           "refinement, learned initial guess for the first solve of each step",
             "plain": plain_rep.pressure_seconds if plain_rep else None,
             "plain_form": "FP64 GMRES(50) on the space-time system",
             "plain_iters": plain_rep.pressure_iters if plain_rep else None,

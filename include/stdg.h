@@ -65,6 +65,10 @@ extern "C" {
                                /* space-time system is G independent symmetric      */
                                /* spatial systems (S^sp (x) I) w = b, x = (I (x) C^-1) w */
                                /* solved by CG: same anchored solution, no GMRES    */
+#define STDG_BICGSTAB 4        /* BiCGStab (van der Vorst): short recurrences, two */
+                               /* operator applies per iteration, no orthogonal     */
+                               /* basis; the viscous solve preconditions it with    */
+                               /* the space-time diagonal blocks as GMRES does      */
 
 typedef struct stdg_mesh stdg_mesh;
 

@@ -17,13 +17,13 @@ from ._lib import (Config, MeshInfo, SolveOpts, SolveReport, StepOpts, StepRepor
                    STDG_AUTO, STDG_CG, STDG_GMRES, STDG_CG_TIME, STDG_GUESS_ZERO,
                    STDG_GUESS_PREVIOUS, STDG_KRYLOV_ZERO, STDG_KRYLOV_PREVIOUS,
                    STDG_KRYLOV_EXTRAPOLATE, STDG_KRYLOV_LEARNED, STDG_LOSS_MSE, STDG_LOSS_RESIDUAL,
-                   STDG_PRECOND_NONE, STDG_PRECOND_BLOCK_JACOBI)
+                   STDG_PRECOND_NONE, STDG_PRECOND_BLOCK_JACOBI, STDG_BICGSTAB)
 
 __all__ = ["Mesh", "Model", "StdgError", "STDG_FP64", "STDG_FP32", "STDG_AUTO",
            "STDG_CG", "STDG_GMRES", "STDG_CG_TIME", "STDG_GUESS_ZERO", "STDG_GUESS_PREVIOUS",
            "STDG_KRYLOV_ZERO", "STDG_KRYLOV_PREVIOUS", "STDG_KRYLOV_EXTRAPOLATE",
            "STDG_KRYLOV_LEARNED", "STDG_LOSS_MSE", "STDG_LOSS_RESIDUAL", "STDG_PRECOND_NONE",
-           "STDG_PRECOND_BLOCK_JACOBI", "solve_opts", "step_opts"]
+           "STDG_PRECOND_BLOCK_JACOBI", "STDG_BICGSTAB", "solve_opts", "step_opts"]
 
 
 def _stream_ptr(stream):

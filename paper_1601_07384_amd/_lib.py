@@ -58,6 +58,7 @@ class SolveReport(ctypes.Structure):
 
 STDG_GUESS_ZERO = 0
 STDG_GUESS_PREVIOUS = 1
+STDG_BICGSTAB = 4
 STDG_PRECOND_NONE = 0
 STDG_PRECOND_BLOCK_JACOBI = 1
 STDG_KRYLOV_ZERO = 0

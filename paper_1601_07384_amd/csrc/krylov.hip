@@ -41,7 +41,15 @@ enum Slot {
     S_CHK = 12,         // fused CG: lagged residual checks (two slots)
     S_TIME = 16,        // G per-time-node sums
     S_ANCH = 32,        // G anchor values
-    S_COUNT = 64
+    S_BRHO = 64,        // BiCGStab: rho = (r^, r) and |r|^2 (adjacent), (t.s) and (t.t) (adjacent),
+    S_BRR = 65,         //   the previous rho, alpha, omega and sigma = (r^, v)
+    S_BTS = 66,
+    S_BTT = 67,
+    S_BRHOP = 68,
+    S_BALPHA = 69,
+    S_BOMEGA = 70,
+    S_BSIG = 71,
+    S_COUNT = 72
 };
 
 __device__ inline double wave_sum(double v) {
@@ -531,6 +539,88 @@ int cg(Ctx& c, const T* b, T* x, T* r, T* p, T* q, double tol_abs, int max_it, i
     return STDG_NOT_CONVERGED;
 }
 
+// ---------------------------------------------------------------- BiCGStab
+// Scalars live in scal: rho = (r^, r_i), its previous value, alpha = rho /
+// (r^, v), omega = (t.s) / (t.t) (see bicgstab()).
+
+__global__ void k_bcg_init(double* __restrict__ scal) {
+    scal[S_BRHO] = scal[S_BRR];
+    scal[S_BRHOP] = 1.0;
+    scal[S_BALPHA] = 1.0;
+    scal[S_BOMEGA] = 1.0;
+}
+
+// p = r + beta (p - omega v), beta = (rho / rho_prev) (alpha / omega)
+template <typename T>
+__global__ void k_bcg_p(T* __restrict__ p, const T* __restrict__ r, const T* __restrict__ v,
+                        const double* __restrict__ scal, int64_t n) {
+    const double om = scal[S_BOMEGA];
+    const double beta = (scal[S_BRHO] / scal[S_BRHOP]) * (scal[S_BALPHA] / om);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (T)((double)r[i] + beta * ((double)p[i] - om * (double)v[i]));
+}
+
+// s = r - alpha v with alpha = rho / sigma (stored for the x update)
+template <typename T>
+__global__ void k_bcg_s(T* __restrict__ s, const T* __restrict__ r, const T* __restrict__ v,
+                        double* __restrict__ scal, int64_t n) {
+    const double alpha = scal[S_BRHO] / scal[S_BSIG];
+    if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_BALPHA] = alpha;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s[i] = (T)((double)r[i] - alpha * (double)v[i]);
+}
+
+// block partials of (a . b) and (a . a): partial[blk] and partial[gridDim.x + blk]
+template <typename T>
+__global__ void __launch_bounds__(RT) k_dot2(const T* __restrict__ a, const T* __restrict__ b, int64_t n,
+                                             double* __restrict__ partial) {
+    __shared__ double sm[RT / 64];
+    double ab = 0.0, aa = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
+        const double ai = (double)a[i];
+        ab += ai * (double)b[i];
+        aa += ai * ai;
+    }
+    const double t0 = block_sum(ab, sm);
+    const double t1 = block_sum(aa, sm);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = t0;
+        partial[gridDim.x + blockIdx.x] = t1;
+    }
+}
+
+// omega = (t.s) / (t.t); x += alpha p + omega s; r = s - omega t; block
+// partials of (r^, r) and (r . r); rho moves to rho_prev
+template <typename T>
+__global__ void __launch_bounds__(RT) k_bcg_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                                               const T* __restrict__ s, const T* __restrict__ t,
+                                               const T* __restrict__ rh, double* __restrict__ scal, int64_t n,
+                                               double* __restrict__ partial) {
+    __shared__ double sm[RT / 64];
+    const double alpha = scal[S_BALPHA];
+    const double tt = scal[S_BTT];
+    const double om = tt > 0.0 ? scal[S_BTS] / tt : 0.0;
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
+        const double si = (double)s[i];
+        x[i] = (T)((double)x[i] + alpha * (double)p[i] + om * si);
+        const T ri = (T)(si - om * (double)t[i]);
+        r[i] = ri;
+        a0 += (double)rh[i] * (double)ri;
+        a1 += (double)ri * (double)ri;
+    }
+    const double t0 = block_sum(a0, sm);
+    const double t1 = block_sum(a1, sm);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = t0;
+        partial[gridDim.x + blockIdx.x] = t1;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[S_BOMEGA] = om;
+        scal[S_BRHOP] = scal[S_BRHO];
+    }
+}
+
 // Restarted GMRES(m) with classical Gram-Schmidt applied twice.
 template <typename T>
 int gmres(Ctx& c, const T* b, T* x, T* r, T* V, int mres, double tol_abs, int max_it, int check_every,
@@ -608,7 +698,59 @@ int run_krylov(Ctx& c, int method, const T* b, T* x, T* r, T* p, T* q, T* V, int
         CK(hipGetLastError());
         return st;
     }
+    if (method == STDG_BICGSTAB)    // r^, s, t in the first three basis vectors (mres >= 2)
+        return bicgstab<T>(c, b, x, r, V, p, q, V + c.n, V + 2 * c.n, tol_abs, max_it, check_every, iters, res);
     return gmres<T>(c, b, x, r, V, mres, tol_abs, max_it, check_every, iters, res);
+}
+
+// BiCGStab (van der Vorst): short recurrences, two operator applies per
+// iteration and no basis to orthogonalise against.  r^ = r_0; scalars and
+// the stopping quantity |r|^2 stay on the device, the host reads |r| every
+// check_every iterations.  Vectors: r, r^, p, v, s, t (s may share x's
+// storage only through the caller's buffers, none alias here).
+template <typename T>
+int bicgstab(Ctx& c, const T* b, T* x, T* r, T* rh, T* p, T* v, T* s, T* t, double tol_abs, int max_it,
+             int check_every, int& iters, double& res_out) {
+    const int64_t n = c.n;
+    const int gb = grid_for(n);
+    CK(Apply<T>::run(c, x, v)); c.applies++;
+    hipLaunchKernelGGL((k_resid<T, T>), dim3(NBLK), dim3(RT), 0, c.s, b, v, r, n, c.partial);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_BRR, (int)FIN_STORE);
+    hipLaunchKernelGGL(k_copy<T>, dim3(gb), dim3(256), 0, c.s, r, rh, n);
+    hipLaunchKernelGGL(k_fill<T>, dim3(gb), dim3(256), 0, c.s, p, (T)0, n);
+    hipLaunchKernelGGL(k_fill<T>, dim3(gb), dim3(256), 0, c.s, v, (T)0, n);
+    hipLaunchKernelGGL(k_bcg_init, dim3(1), dim3(1), 0, c.s, c.scal);
+    CK(hipGetLastError());
+    double rr;
+    if (int e = read_scal(c, S_BRR, rr)) return e;
+    iters = 0;
+    res_out = std::sqrt(rr);
+    if (!std::isfinite(res_out)) { set_error("non-finite residual in BiCGStab"); return STDG_ERR_NUMERIC; }
+    if (res_out <= tol_abs) return STDG_OK;
+    while (iters < max_it) {
+        hipLaunchKernelGGL(k_bcg_p<T>, dim3(gb), dim3(256), 0, c.s, p, r, v, c.scal, n);
+        CK(Apply<T>::run(c, p, v)); c.applies++;
+        hipLaunchKernelGGL((k_dot<T, T>), dim3(NBLK), dim3(RT), 0, c.s, rh, v, n, c.partial);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_BSIG,
+                           (int)FIN_STORE);
+        hipLaunchKernelGGL(k_bcg_s<T>, dim3(gb), dim3(256), 0, c.s, s, r, v, c.scal, n);
+        CK(Apply<T>::run(c, s, t)); c.applies++;
+        hipLaunchKernelGGL(k_dot2<T>, dim3(NBLK), dim3(RT), 0, c.s, t, s, n, c.partial);
+        hipLaunchKernelGGL(k_fin_multi, dim3(2), dim3(RT), 0, c.s, c.partial, NBLK, c.scal + S_BTS,
+                           (double*)nullptr, 0.0);
+        hipLaunchKernelGGL(k_bcg_xr<T>, dim3(NBLK), dim3(RT), 0, c.s, x, r, p, s, t, rh, c.scal, n, c.partial);
+        hipLaunchKernelGGL(k_fin_multi, dim3(2), dim3(RT), 0, c.s, c.partial, NBLK, c.scal + S_BRHO,
+                           (double*)nullptr, 0.0);
+        CK(hipGetLastError());
+        ++iters;
+        if (iters % check_every == 0 || iters == max_it) {
+            if (int e = read_scal(c, S_BRR, rr)) return e;
+            if (!std::isfinite(rr)) { set_error("non-finite residual in BiCGStab"); return STDG_ERR_NUMERIC; }
+            res_out = std::sqrt(rr);
+            if (res_out <= tol_abs) return STDG_OK;
+        }
+    }
+    return STDG_NOT_CONVERGED;
 }
 
 int ensure_workspace(stdg_mesh* m, int mres, bool need32) {
@@ -699,9 +841,16 @@ int viscous_solve(stdg_mesh* m, const double* b, double* x, const stdg_solve_opt
     double* q = work + 2 * n;
     double* V = work + 3 * n;
     const int method = o.method == STDG_AUTO ? STDG_GMRES : o.method;
-    const bool pre = method == STDG_GMRES;
+    const bool pre = method == STDG_GMRES || method == STDG_BICGSTAB;
     if (method == STDG_GMRES && o.restart < 1) { set_error("viscous GMRES restart must be >= 1"); return STDG_ERR_ARG; }
-    if (method != STDG_GMRES && method != STDG_CG) { set_error("viscous method must be CG or GMRES"); return STDG_ERR_ARG; }
+    if (method == STDG_BICGSTAB && o.restart < 2) {
+        set_error("viscous BiCGStab keeps r^, s, t in the first three basis vectors: restart must be >= 2");
+        return STDG_ERR_ARG;
+    }
+    if (method != STDG_GMRES && method != STDG_CG && method != STDG_BICGSTAB) {
+        set_error("viscous method must be CG, GMRES or BiCGStab");
+        return STDG_ERR_ARG;
+    }
     double* bp = work + (int64_t)(o.restart + 5) * n;
     c.tmp = work + (int64_t)(o.restart + 4) * n;
     hipLaunchKernelGGL((k_dot<double, double>), dim3(NBLK), dim3(RT), 0, s, b, b, n, c.partial);
@@ -776,7 +925,7 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
     if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
     stdg_solve_opts o = *opts;
     if (o.method == STDG_AUTO) o.method = (m->G == 1) ? STDG_CG : STDG_GMRES;
-    if (o.method != STDG_CG && o.method != STDG_GMRES && o.method != STDG_CG_TIME) {
+    if (o.method != STDG_CG && o.method != STDG_GMRES && o.method != STDG_CG_TIME && o.method != STDG_BICGSTAB) {
         set_error("unknown method");
         return STDG_ERR_ARG;
     }
@@ -790,7 +939,7 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
     if (o.precision != STDG_FP64 && o.precision != STDG_FP32) { set_error("bad precision"); return STDG_ERR_ARG; }
     const bool ir = o.precision == STDG_FP32;
     if (ir && (!(o.inner_rtol > 0.0) || o.max_outer < 1)) { set_error("bad refinement options"); return STDG_ERR_ARG; }
-    const int mres = (o.method == STDG_GMRES) ? o.restart : 0;
+    const int mres = (o.method == STDG_GMRES) ? o.restart : (o.method == STDG_BICGSTAB ? 2 : 0);
     if (int e = ensure_workspace(m, mres, ir)) return e;
     Workspace& w = m->ws;
     Ctx c;

@@ -56,7 +56,7 @@ def from_dev_dual(t, fmap, F, Nst):
     return out
 
 
-def run_both(n, p, pg, periodic, nu, dt, n_pic, field):
+def run_both(n, p, pg, periodic, nu, dt, n_pic, field, viscous_method=None):
     X, T = kuhn_mesh(n)
     om = OracleMesh(X, T, periodic=periodic)
     ops = SpaceTimeOperators(om, p, pg, dt)
@@ -82,8 +82,10 @@ def run_both(n, p, pg, periodic, nu, dt, n_pic, field):
     assert np.abs(vh0_g - vh0).max() <= 1e-11 * np.abs(vh0).max()
     pg_dev = torch.zeros(m.E * m.Nst, dtype=torch.float64, device=DEV)
     gd = to_dev_main(g, perm) if not periodic else None
-    rep = m.picard_step(vhat, vbar, pg_dev, gd, n_picard=n_pic,
-                        pressure={"rtol": 1e-13}, viscous={"rtol": 1e-13})
+    visc = {"rtol": 1e-13}
+    if viscous_method is not None:
+        visc.update(method=viscous_method, restart=30)
+    rep = m.picard_step(vhat, vbar, pg_dev, gd, n_picard=n_pic, pressure={"rtol": 1e-13}, viscous=visc)
     vh_g = from_dev_dual(vhat, fmap, m.n_face, m.Nst)
     vb_g = from_dev_main(vbar, perm, m.E, m.Nst)
     p_g = np.empty((m.E, m.Nst))
@@ -109,6 +111,19 @@ def test_picard_step_matches_oracle(n, p, pg, periodic, nu, dt, n_pic, field):
     assert np.abs(vb_g - vb_o).max() <= 1e-9 * np.abs(vb_o).max()
     assert np.abs(p_g - p_o).max() <= 1e-8 * np.abs(p_o).max()
     assert rep.max_pressure_residual <= 1e-12
+
+
+@pytest.mark.parametrize("n,p,pg,periodic,nu,dt,n_pic,field", [CASES[1], CASES[4]])
+def test_picard_step_bicgstab_viscous(n, p, pg, periodic, nu, dt, n_pic, field):
+    """The same step with the viscous systems solved by preconditioned
+    BiCGStab instead of GMRES."""
+    print(f"picard bicgstab case n={n} p={p} pg={pg} periodic={periodic}", flush=True)
+    (vh_o, vb_o, p_o), (vh_g, vb_g, p_g), rep, _ = run_both(n, p, pg, periodic, nu, dt, n_pic, field,
+                                                           viscous_method=P.STDG_BICGSTAB)
+    assert np.abs(vh_g - vh_o).max() <= 1e-9 * np.abs(vh_o).max()
+    assert np.abs(vb_g - vb_o).max() <= 1e-9 * np.abs(vb_o).max()
+    assert np.abs(p_g - p_o).max() <= 1e-8 * np.abs(p_o).max()
+    assert rep.max_viscous_residual <= 1e-12
 
 
 def test_picard_step_divergence_free_on_device():
