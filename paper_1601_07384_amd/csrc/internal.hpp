@@ -93,6 +93,8 @@ struct PicardDevice {
     int32_t* frf = nullptr;          // [F] right local face
     double* work = nullptr;          // step workspace
     size_t work_len = 0;
+    double* conv_tmp = nullptr;      // convection sums per time point [qt][3][E][N]
+    size_t conv_len = 0;
 };
 
 }  // namespace stdg

@@ -38,6 +38,7 @@ int model_predict(stdg_model* md, const stdg_mesh* m, const double* P, const dou
 int device_dots(stdg_mesh* m, int k, const double* const* a, const double* const* b, int64_t n, hipStream_t s,
                 double* out);
 bool fast_rows_supported(const stdg_mesh* m);
+hipError_t fast_convection(const stdg_mesh* m, const double* vbar, const double* vbc, double* ups, hipStream_t s);
 hipError_t fast_dualgrad(const stdg_mesh* m, const double* p, double dt, double* w, hipStream_t s);
 hipError_t fast_goback(const stdg_mesh* m, const double* vbar, const double* vbdry, double* out, int64_t f0,
                        int64_t f1, hipStream_t s);

@@ -467,6 +467,10 @@ hipError_t launch_conv_ng(const stdg_mesh* m, const double* vbar, const double* 
 
 hipError_t launch_convection(const stdg_mesh* m, const double* vbar, const double* vbc, double* ups,
                              hipStream_t s) {
+    {
+        const hipError_t e = fast_convection(m, vbar, vbc, ups, s);
+        if (e != hipErrorNotSupported) return e;
+    }
 #define STDG_CV(n, g) \
     if (m->N == n && m->G == g) return launch_conv_ng<n, g>(m, vbar, vbc, ups, s);
     STDG_CV(4, 1) STDG_CV(4, 2) STDG_CV(4, 3) STDG_CV(4, 4) STDG_CV(4, 5)
@@ -621,7 +625,7 @@ void free_picard(stdg_mesh* m) {
                     (void*)d.Tm, (void*)d.TW, (void*)d.W, (void*)d.g0g1, (void*)d.g1, (void*)d.tet_face,
                     (void*)d.fl, (void*)d.fr, (void*)d.flf, (void*)d.frf, (void*)d.work, (void*)d.DV,
                     (void*)d.SVt, (void*)d.MIt, (void*)d.At, (void*)d.GBt, (void*)d.QTt, (void*)d.USt,
-                    (void*)d.UNt, (void*)d.BBt})
+                    (void*)d.UNt, (void*)d.BBt, (void*)d.conv_tmp})
         if (p) (void)hipFree(p);
     d = PicardDevice();
 }

@@ -271,6 +271,213 @@ hipError_t blockdiag_ng(const stdg_mesh* m, const double* x, double* y, hipStrea
     return hipGetLastError();
 }
 
+
+// ------------------------------------------------------------- convection
+// Space-time DG convection with the Rusanov flux (eq. convdg), restructured
+// for throughput: a wavefront takes 64 consecutive elements (one per lane)
+// at one time point t of the rule.  Elements are stored class-chunked, so the
+// 64 lanes normally share one geometry class and every table entry (volume
+// and face basis values, their gradients, weights, the class Jacobian and
+// normals) is the same for the whole wavefront: it is read once through the
+// scalar cache and applied by every lane.  A lane holds its element's
+// velocity coefficients at time t (3 N values) in registers and, in each of
+// two passes over the points, half of the 3 N output sums; the neighbour's
+// coefficients across the face in hand are staged in the lane's own LDS
+// column.  The per-time-point sums go to tmp[t][3][E][N]
+// and kf_conv_combine weights them with the time basis (fixed order).  A
+// wavefront that mixes classes (the tail of a mesh with many classes) runs
+// the classes present one after the other, the other lanes masked.
+template <int N, int G>
+__global__ void __launch_bounds__(64) kf_convection(
+    const double* __restrict__ vbar, const double* __restrict__ vbc, const int32_t* __restrict__ cls,
+    const int32_t* __restrict__ nbr, const int64_t* __restrict__ tet_face, const double* __restrict__ cJinv,
+    const double* __restrict__ cdet, const double* __restrict__ cnrm, const double* __restrict__ PHf,
+    const double* __restrict__ PHn, const double* __restrict__ FW, const double* __restrict__ PHv,
+    const double* __restrict__ dPHv, const double* __restrict__ wv, const double* __restrict__ tw,
+    const double* __restrict__ gq, int nqv, int nqf, int qt, double* __restrict__ tmp, int64_t E, int64_t F) {
+    constexpr int KH = (N + 1) / 2;              // test functions per pass (two passes)
+    __shared__ double xn_s[3 * N * 64];          // [3 N][lane]: neighbour coefficients at t
+    const int lane = threadIdx.x;
+    const int t = blockIdx.x % qt;
+    const int64_t i = (int64_t)(blockIdx.x / qt) * 64 + lane;
+    const bool valid = i < E;
+    const int c = valid ? cls[i] : -1;
+    double gt[G];
+#pragma unroll
+    for (int b = 0; b < G; ++b) gt[b] = gq[t * G + b];
+    const double wt = tw[t];
+    // own coefficients at time point t (staged through the lane's LDS column
+    // one component at a time, which bounds the loads in flight)
+#pragma unroll 1
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            double s = 0.0;
+            if (valid)
+#pragma unroll
+                for (int b = 0; b < G; ++b) s += gt[b] * vbar[((cc * E + i) * G + b) * N + n];
+            xn_s[(cc * N + n) * 64 + lane] = s;
+        }
+    double xt[3][N];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+        for (int n = 0; n < N; ++n) xt[cc][n] = xn_s[(cc * N + n) * 64 + lane];
+#pragma unroll 1
+    for (int k0 = 0; k0 < N; k0 += KH) {
+        double o[3][KH];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+            for (int kk = 0; kk < KH; ++kk) o[cc][kk] = 0.0;
+        for (uint64_t todo = __ballot(valid); todo;) {
+            const int cur = __builtin_amdgcn_readlane(c, __builtin_ctzll(todo));
+            const bool mine = valid && c == cur;
+            todo &= ~__ballot(mine);
+            if (!mine) continue;
+            const double* Ji = cJinv + (int64_t)cur * 9;
+            const double det = cdet[cur];
+            // volume points: F_cd = v_c v_d pulled back by J^-T, tested with grad phi
+#pragma unroll 1
+            for (int q = 0; q < nqv; ++q) {
+                const double* ph = PHv + (int64_t)q * N;
+                double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int n = 0; n < N; ++n) {
+                    const double pn = ph[n];
+                    v[0] += pn * xt[0][n];
+                    v[1] += pn * xt[1][n];
+                    v[2] += pn * xt[2][n];
+                }
+                const double w = wt * wv[q] * det;
+                double fl[3][3];
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const double se = Ji[e * 3 + 0] * v[0] + Ji[e * 3 + 1] * v[1] + Ji[e * 3 + 2] * v[2];
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) fl[cc][e] = w * v[cc] * se;
+                }
+                const double* dp = dPHv + ((int64_t)q * N + k0) * 3;
+#pragma unroll
+                for (int kk = 0; kk < KH; ++kk) {
+                    if (k0 + kk >= N) break;
+                    const double d0 = dp[3 * kk], d1 = dp[3 * kk + 1], d2 = dp[3 * kk + 2];
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) o[cc][kk] -= d0 * fl[cc][0] + d1 * fl[cc][1] + d2 * fl[cc][2];
+                }
+            }
+            // faces: own trace against the neighbour's (or the boundary data)
+#pragma unroll 1
+            for (int f = 0; f < 4; ++f) {
+                // neighbour element k, or the boundary face's prescribed data
+                const int64_t k = nbr[4 * i + f];
+                const double* xp = k >= 0 ? vbar + k * G * N : vbc + tet_face[4 * i + f] * G * N;
+                const int64_t cstr = (k >= 0 ? E : F) * G * N;
+#pragma unroll 1
+                for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+                    for (int n = 0; n < N; ++n) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int b = 0; b < G; ++b) s += gt[b] * xp[cc * cstr + b * N + n];
+                        xn_s[(cc * N + n) * 64 + lane] = s;
+                    }
+                const double* nr = cnrm + (int64_t)cur * 12 + f * 3;
+                const double n0 = nr[0], n1 = nr[1], n2 = nr[2];
+#pragma unroll 1
+                for (int q = 0; q < nqf; ++q) {
+                    const int64_t off = ((int64_t)cur * 4 + f) * nqf + q;
+                    const double* pf = PHf + off * N;
+                    const double* pn = PHn + off * N;
+                    // the neighbour's coefficients are re-read from LDS at every
+                    // point (an opaque offset keeps the compiler from hoisting
+                    // them into registers next to the element's own)
+                    int col = lane;
+                    asm volatile("" : "+v"(col));
+                    const double* xnl = xn_s + col;
+                    double vm[3] = {0.0, 0.0, 0.0}, vp[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int n = 0; n < N; ++n) {
+                        const double a = pf[n], bq = pn[n];
+#pragma unroll
+                        for (int cc = 0; cc < 3; ++cc) {
+                            vm[cc] += a * xt[cc][n];
+                            vp[cc] += bq * xnl[(cc * N + n) * 64];
+                        }
+                    }
+                    const double unm = vm[0] * n0 + vm[1] * n1 + vm[2] * n2;
+                    const double unp = vp[0] * n0 + vp[1] * n1 + vp[2] * n2;
+                    const double am = sqrt(vm[0] * vm[0] + vm[1] * vm[1] + vm[2] * vm[2]);
+                    const double ap = sqrt(vp[0] * vp[0] + vp[1] * vp[1] + vp[2] * vp[2]);
+                    const double smax = 2.0 * (am > ap ? am : ap);
+                    const double w = wt * FW[off];
+                    double fc[3];
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc)
+                        fc[cc] = w * (0.5 * (vp[cc] * unp + vm[cc] * unm) - 0.5 * smax * (vp[cc] - vm[cc]));
+#pragma unroll
+                    for (int kk = 0; kk < KH; ++kk) {
+                        if (k0 + kk >= N) break;
+                        const double a = pf[k0 + kk];
+#pragma unroll
+                        for (int cc = 0; cc < 3; ++cc) o[cc][kk] += a * fc[cc];
+                    }
+                }
+            }
+        }
+        if (valid)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+                for (int kk = 0; kk < KH; ++kk)
+                    if (k0 + kk < N) tmp[(((int64_t)t * 3 + cc) * E + i) * N + k0 + kk] = o[cc][kk];
+    }
+}
+
+// ups[c][e][a][k] = dt sum_t gq[t][a] tmp[t][c][e][k]
+template <int N, int G>
+__global__ void kf_conv_combine(const double* __restrict__ tmp, const double* __restrict__ gq, int qt, double dt,
+                                double* __restrict__ ups, int64_t E) {
+    const int64_t n = 3 * E * N;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t ce = idx / N;
+        const int k = (int)(idx - ce * N);
+        double acc[G];
+#pragma unroll
+        for (int a = 0; a < G; ++a) acc[a] = 0.0;
+        for (int t = 0; t < qt; ++t) {
+            const double v = tmp[(int64_t)t * n + idx];
+#pragma unroll
+            for (int a = 0; a < G; ++a) acc[a] += gq[t * G + a] * v;
+        }
+#pragma unroll
+        for (int a = 0; a < G; ++a) ups[(ce * G + a) * N + k] = dt * acc[a];
+    }
+}
+
+
+template <int N, int G>
+hipError_t convection_ng(const stdg_mesh* m, const double* vbar, const double* vbc, double* ups, hipStream_t s) {
+    const PicardTables& t = m->pt;
+    PicardDevice& d = const_cast<stdg_mesh*>(m)->pd;
+    const size_t need = (size_t)t.qt * 3 * m->E * N;
+    if (d.conv_len < need) {
+        if (d.conv_tmp) (void)hipFree(d.conv_tmp);
+        d.conv_tmp = nullptr;
+        d.conv_len = 0;
+        const hipError_t e = hipMalloc(&d.conv_tmp, need * sizeof(double));
+        if (e != hipSuccess) return e;
+        d.conv_len = need;
+    }
+    const unsigned blocks = (unsigned)(((m->E + 63) / 64) * t.qt);
+    hipLaunchKernelGGL((kf_convection<N, G>), dim3(blocks), dim3(64), 0, s, vbar, vbc, m->d.cls, m->d.nbr,
+                       d.tet_face, d.cJinv, d.cdet, d.cnrm, d.PHf, d.PHn, d.FW, d.PHv, d.dPHv, d.wv, d.tw, d.gq,
+                       t.nqv, t.nqf, t.qt, d.conv_tmp, m->E, (int64_t)m->faces.size());
+    const int64_t n = 3 * m->E * N;
+    hipLaunchKernelGGL((kf_conv_combine<N, G>), dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256),
+                       0, s, d.conv_tmp, d.gq, t.qt, m->cfg.dt, ups, m->E);
+    return hipGetLastError();
+}
 }  // namespace
 
 #define STDG_FAST_N(CALL)                          \
@@ -302,6 +509,17 @@ hipError_t fast_visc_rhs(const stdg_mesh* m, const double* vprev, const double* 
     STDG_FAST_N(visc_rhs(m, vprev, ups, lam, vbc, rhs, s))
 }
 #undef STDG_FAST_N
+
+// convection for p <= 3 (the element's 3 N coefficients and 3 N sums in registers)
+hipError_t fast_convection(const stdg_mesh* m, const double* vbar, const double* vbc, double* ups, hipStream_t s) {
+#define STDG_CV(n, g) \
+    if (m->N == n && m->G == g) return convection_ng<n, g>(m, vbar, vbc, ups, s);
+    STDG_CV(4, 1) STDG_CV(4, 2) STDG_CV(4, 3) STDG_CV(4, 4) STDG_CV(4, 5)
+    STDG_CV(10, 1) STDG_CV(10, 2) STDG_CV(10, 3) STDG_CV(10, 4) STDG_CV(10, 5)
+    STDG_CV(20, 1) STDG_CV(20, 2) STDG_CV(20, 3) STDG_CV(20, 4) STDG_CV(20, 5)
+#undef STDG_CV
+    return hipErrorNotSupported;
+}
 
 // NG = N G up to 40 (p <= 3 with p_gamma <= 1, or p <= 2 with p_gamma <= 3)
 hipError_t fast_blockdiag(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
