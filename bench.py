@@ -48,8 +48,8 @@ N_HEX, P_DEG, P_GAMMA, DT, NU = 24, 3, 1, 1e-3, 1e-3
 # HBM bytes per launch of k_cg_op<20, true> from rocprofv3 FETCH_SIZE (x 2.0)
 # and WRITE_SIZE (x 1.0), calibrated by a device copy of known size; valid
 # only for the kernel source they were measured on (sha256 prefix).
-MEASURED_TRAFFIC = {"source": "paper_1601_07384_amd/csrc/cg_fused.hip", "sha256": "b550fc66f4ba4724",
-                    "bytes": 117310 * 1024.0}
+MEASURED_TRAFFIC = {"source": "paper_1601_07384_amd/csrc/cg_fused.hip", "sha256": "fe6057e5558e2004",
+                    "bytes": 117609.2 * 1024.0}
 FP64_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0

@@ -36,7 +36,7 @@
 // CG update of it, the products and the dot products need no lane exchange.
 // The class blocks are stored in MFMA operand order (upload_cg_operands):
 // float4 i of lane l at [class][i][l]; a workgroup copies the operands of its
-// class into LDS once and its four wavefronts read them from there.  All
+// class into LDS once and its wavefronts read them from there.  All
 // global loads of a wavefront are issued before the first is used; rows that
 // do not exist (boundary faces, the ragged end of the last tile) read through
 // a buffer resource at an offset past its end, which returns zeros, and
@@ -84,6 +84,7 @@ typedef __amdgpu_buffer_rsrc_t Rsrc;
 
 constexpr uint32_t OOB = 0x80000000u;   // byte offset past every buffer: loads give 0, stores are dropped
 constexpr int RED_T = 1024;             // threads of the one-block reductions
+constexpr int WPB = 4;                  // wavefronts per workgroup of the operator kernel (8 measured slower)
 constexpr int NPART = 5;                // partial dot products per block ...
 constexpr int PSTRIDE = 8;              // ... stored with this stride (doubles)
 
@@ -244,10 +245,11 @@ struct TilePos {
     int a;
     bool active;
 };
+template <int WB>
 __device__ inline TilePos tile_pos(int wave, int32_t E, int32_t G, uint64_t gmul) {
     TilePos t;
     t.lblock = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
-    const uint32_t wid = t.lblock * 4 + (uint32_t)__builtin_amdgcn_readfirstlane(wave);
+    const uint32_t wid = t.lblock * WB + (uint32_t)__builtin_amdgcn_readfirstlane(wave);
     t.tile = (uint32_t)(((uint64_t)wid * gmul) >> 32);
     t.active = t.tile < ((uint32_t)E + 15) / 16;
     t.a = t.active ? (int)(wid - t.tile * (uint32_t)G) : 0;
@@ -255,7 +257,7 @@ __device__ inline TilePos tile_pos(int wave, int32_t E, int32_t G, uint64_t gmul
 }
 
 template <int N, bool ITER>
-__global__ void __launch_bounds__(256) k_cg_op(const float* __restrict__ A, const int32_t* __restrict__ cls,
+__global__ void __launch_bounds__(64 * WPB) k_cg_op(const float* __restrict__ A, const int32_t* __restrict__ cls,
                                                const int32_t* __restrict__ nbr, float* x, const float* r_in,
                                                const float* p_in, const float* q_in, float* r_out, float* p_out,
                                                float* q_out, const double* __restrict__ ab, float cscale,
@@ -264,7 +266,7 @@ __global__ void __launch_bounds__(256) k_cg_op(const float* __restrict__ A, cons
     typedef SliceShape<N> S;
     constexpr int W = S::W, REM = S::REM, KS = S::KS, MT = S::MT, NB = S::NB, NA = S::NA, NI = S::NI,
                   NT = S::NT;
-    __shared__ double sh[4 * NPART];
+    __shared__ double sh[WPB * NPART];
     __shared__ f4 As[NT * 16];          // operands of the block's class, [i][lane]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, kk = lane >> 4;
@@ -274,7 +276,7 @@ __global__ void __launch_bounds__(256) k_cg_op(const float* __restrict__ A, cons
         alpha = (float)ab[0];
         beta = (float)ab[1];
     }
-    const TilePos tp = tile_pos(wave, E, G, gmul);
+    const TilePos tp = tile_pos<WPB>(wave, E, G, gmul);
     const int a = tp.a;
     const int32_t e = (tp.active ? (int32_t)tp.tile * 16 : 0) + col;
     const bool vcol = tp.active && e < E;
@@ -297,7 +299,7 @@ __global__ void __launch_bounds__(256) k_cg_op(const float* __restrict__ A, cons
     const int c = vcol ? cl : -1;
     // class of the block: that of its first element, whose operands the four
     // wavefronts share through LDS (copied once per block)
-    const uint32_t tile_b = (uint32_t)(((uint64_t)(tp.lblock * 4) * gmul) >> 32);
+    const uint32_t tile_b = (uint32_t)(((uint64_t)(tp.lblock * WPB) * gmul) >> 32);
     const int cb = tile_b * 16 < (uint32_t)E ? cls[tile_b * 16] : 0;
     // gather: every load of the wavefront (rows, own x, then the block's
     // share of the operand copy) is in flight before the first use
@@ -328,8 +330,8 @@ __global__ void __launch_bounds__(256) k_cg_op(const float* __restrict__ A, cons
         const f4* src = A4 + (size_t)cb * NT * 16;
         const int wu = __builtin_amdgcn_readfirstlane(wave);
 #pragma unroll
-        for (int j = 0; j < (NT * 16 + 255) / 256; ++j) {
-            const int i0 = 256 * j + 64 * wu;
+        for (int j = 0; j < (NT * 16 + 64 * WPB - 1) / (64 * WPB); ++j) {
+            const int i0 = 64 * WPB * j + 64 * wu;
             if (i0 < NT * 16)
                 __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(src + i0 + lane),
                                                  (__attribute__((address_space(3))) void*)(As + i0), 16, 0, 0);
@@ -452,8 +454,10 @@ __global__ void __launch_bounds__(256) k_cg_op(const float* __restrict__ A, cons
     __syncthreads();
     if (threadIdx.x < NPART) {
         const int cc = threadIdx.x;
-        part_out[PSTRIDE * blockIdx.x + cc] =
-            ((sh[cc] + sh[NPART + cc]) + sh[2 * NPART + cc]) + sh[3 * NPART + cc];
+        double t = 0.0;
+#pragma unroll
+        for (int wv = 0; wv < WPB; ++wv) t += sh[wv * NPART + cc];
+        part_out[PSTRIDE * blockIdx.x + cc] = t;
     }
 }
 
@@ -466,7 +470,7 @@ __global__ void __launch_bounds__(256) k_cg_prec(const float* __restrict__ A, co
     constexpr int W = S::W, REM = S::REM, KS = S::KS, MT = S::MT, NA = S::NA, NI = S::NI, NT = S::NT;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, kk = lane >> 4;
-    const TilePos tp = tile_pos(wave, E, G, gmul);
+    const TilePos tp = tile_pos<4>(wave, E, G, gmul);
     const int32_t e = (tp.active ? (int32_t)tp.tile * 16 : 0) + col;
     const bool vcol = tp.active && e < E;
     const Rsrc rc = make_rsrc(cls, 4u * (uint32_t)E);
@@ -496,6 +500,11 @@ __global__ void __launch_bounds__(256) k_cg_prec(const float* __restrict__ A, co
     if (REM > 0) bstore<1>(ryo, offr, &o[W]);
 }
 
+int64_t prec_blocks(const stdg_mesh* m) {
+    const int64_t waves = (m->E + 15) / 16 * m->G;
+    return ((waves + 3) / 4 + 7) / 8 * 8;
+}
+
 uint64_t g_multiplier(const stdg_mesh* m) {
     return ((uint64_t(1) << 32) + (uint64_t)m->G - 1) / (uint64_t)m->G;
 }
@@ -505,7 +514,7 @@ hipError_t op_n(const stdg_mesh* m, float* x, const float* r_in, const float* p_
                 float* p_out, float* q_out, const double* ab, float cscale, int precond, double* part_out,
                 hipStream_t s) {
     const uint32_t vbytes = (uint32_t)(4 * m->E * m->G * m->N);
-    hipLaunchKernelGGL((k_cg_op<N, ITER>), dim3((unsigned)cg_op_blocks(m)), dim3(256), 0, s, m->d.aop32, m->d.cls,
+    hipLaunchKernelGGL((k_cg_op<N, ITER>), dim3((unsigned)cg_op_blocks(m)), dim3(64 * WPB), 0, s, m->d.aop32, m->d.cls,
                        m->d.nbr, x, r_in, p_in, q_in, r_out, p_out, q_out, ab, cscale, precond, (int32_t)m->E,
                        (int32_t)m->G, g_multiplier(m), vbytes, part_out);
     return hipGetLastError();
@@ -571,7 +580,7 @@ int upload_cg_operands(stdg_mesh* m) {
 
 int64_t cg_op_blocks(const stdg_mesh* m) {
     const int64_t waves = (m->E + 15) / 16 * m->G;
-    return ((waves + 3) / 4 + 7) / 8 * 8;       // a multiple of the 8 XCDs
+    return ((waves + WPB - 1) / WPB + 7) / 8 * 8;       // a multiple of the 8 XCDs
 }
 
 int64_t cg_partial_len(const stdg_mesh* m) { return PSTRIDE * cg_op_blocks(m); }
@@ -605,7 +614,7 @@ hipError_t launch_cg_prec_f32(const stdg_mesh* m, const float* x, float* y, floa
     const uint32_t vbytes = (uint32_t)(4 * m->E * m->G * m->N);
 #define STDG_OPN(n)                                                                                            \
     case n:                                                                                                    \
-        hipLaunchKernelGGL(k_cg_prec<n>, dim3((unsigned)cg_op_blocks(m)), dim3(256), 0, s, m->d.aop32, m->d.cls, \
+        hipLaunchKernelGGL(k_cg_prec<n>, dim3((unsigned)prec_blocks(m)), dim3(256), 0, s, m->d.aop32, m->d.cls, \
                            x, y, scale, (int32_t)m->E, (int32_t)m->G, g_multiplier(m), vbytes);                 \
         return hipGetLastError();
     switch (m->N) {

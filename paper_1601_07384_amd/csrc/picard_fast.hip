@@ -382,13 +382,14 @@ __global__ void __launch_bounds__(64) kf_convection(
                         for (int b = 0; b < G; ++b) s += gt[b] * xp[cc * cstr + b * N + n];
                         xn_s[(cc * N + n) * 64 + lane] = s;
                     }
-                const double* nr = cnrm + (int64_t)cur * 12 + f * 3;
+                const double* nr = cnrm + __builtin_amdgcn_readfirstlane(cur * 12 + f * 3);
                 const double n0 = nr[0], n1 = nr[1], n2 = nr[2];
 #pragma unroll 1
                 for (int q = 0; q < nqf; ++q) {
-                    const int64_t off = ((int64_t)cur * 4 + f) * nqf + q;
-                    const double* pf = PHf + off * N;
-                    const double* pn = PHn + off * N;
+                    // (wavefront-uniform: the tables are read through the scalar cache)
+                    const int off = __builtin_amdgcn_readfirstlane((cur * 4 + f) * nqf + q);
+                    const double* pf = PHf + (int64_t)off * N;
+                    const double* pn = PHn + (int64_t)off * N;
                     // the neighbour's coefficients are re-read from LDS at every
                     // point (an opaque offset keeps the compiler from hoisting
                     // them into registers next to the element's own)

@@ -41,6 +41,24 @@ def test_library_exports_every_declared_symbol():
     assert names <= bound, names - bound
 
 
+def test_binding_constants_match_header():
+    """Every integer #define of the header that the binding names has the
+    header's value, and the binding names all method, precision,
+    preconditioner, guess and loss constants."""
+    txt = open(os.path.join(ROOT, "include", "stdg.h")).read()
+    defs = {k: int(v) for k, v in re.findall(r"#define\s+(STDG_[A-Z0-9_]+)\s+(-?\d+)\b", txt)}
+    assert len(defs) >= 15
+    for k, v in defs.items():
+        if hasattr(_lib, k):
+            assert getattr(_lib, k) == v, k
+    for prefix in ("STDG_FP", "STDG_PRECOND_", "STDG_KRYLOV_", "STDG_LOSS_"):
+        for k in defs:
+            if k.startswith(prefix):
+                assert hasattr(_lib, k), k
+    for k in ("STDG_AUTO", "STDG_CG", "STDG_GMRES", "STDG_CG_TIME", "STDG_BICGSTAB"):
+        assert getattr(_lib, k) == defs[k], k
+
+
 @pytest.mark.parametrize("n,p,pg,periodic,jitter", [
     (2, 2, 0, False, 0.0), (2, 1, 1, False, 0.15), (3, 2, 1, True, 0.0),
     (2, 3, 0, False, 0.1), (2, 2, 2, False, 0.0)])
