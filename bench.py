@@ -254,7 +254,8 @@ def main():
         "step": {"pressure_s": first.pressure_seconds, "viscous_s": first.viscous_seconds,
                  "pressure_iters": first.pressure_iters, "viscous_iters": first.viscous_iters,
                  "pressure_applies": first.pressure_applies,
-                 "max_pressure_residual": first.max_pressure_residual},
+                 "max_pressure_residual": first.max_pressure_residual,
+                 "all_timed_steps_converged": all(r.status == P.STDG_OK for r in reps)},
         "pressure_solve_s": {
             "chosen": first.pressure_seconds,
             "chosen_form": "time-decoupled CG, block-Jacobi preconditioned, FP32 inner / FP64 "

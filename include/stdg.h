@@ -274,6 +274,9 @@ typedef struct {
     double first_initial_residual;     /* ||b - S x0|| / ||b|| of its guess   */
     double pressure_fused_iter_us;     /* fused_iter_us over the step's solves */
     double guess_weight_network;       /* g of STDG_KRYLOV_LEARNED (else 0)    */
+    int32_t status;             /* the step's return code: STDG_OK, or      */
+                                /* STDG_NOT_CONVERGED when a pressure or    */
+                                /* viscous solve stopped above its rtol     */
 } stdg_step_report;
 
 /* Defaults: n_picard 0, zero pressure guess, solve defaults, viscous rtol
@@ -287,7 +290,10 @@ void stdg_step_opts_default(stdg_step_opts* opts);
  * n+1 on exit; g_nodal [3][E][G][N]: Dirichlet velocity at the element nodes
  * of slab n+1 (only elements with boundary faces are read; NULL allowed on a
  * mesh without boundary faces).  Device pointers; workspace is owned by the
- * mesh handle.  Synchronises `stream`. */
+ * mesh handle.  Meshes with p_gamma > 4 are rejected (STDG_ERR_ARG).
+ * Synchronises `stream`.  Returns STDG_OK; STDG_NOT_CONVERGED
+ * when the step ran to its end but a pressure or viscous solve stopped above
+ * its rtol (the report's residuals say which); or an error. */
 int stdg_picard_step(const stdg_mesh* mesh, double* vhat, double* vbar, double* p,
                      const double* g_nodal, const stdg_step_opts* opts,
                      stdg_step_report* report, void* stream);

@@ -172,9 +172,9 @@ class Mesh:
                 self._check_any(t, n * self.E * self.Nst)
         rep = StepReport()
         g = _ptr(g_nodal) if g_nodal is not None else None
-        _lib.check(self._lib.stdg_picard_step(self._h, _ptr(vhat), _ptr(vbar), _ptr(p), g,
-                                              ctypes.byref(o), ctypes.byref(rep),
-                                              _stream_ptr(stream)))
+        code = self._lib.stdg_picard_step(self._h, _ptr(vhat), _ptr(vbar), _ptr(p), g,
+                                          ctypes.byref(o), ctypes.byref(rep), _stream_ptr(stream))
+        _lib.check(code, allow=(STDG_OK, STDG_NOT_CONVERGED))
         return rep
 
     def dual_from_main(self, vbar, vhat, stream=None):

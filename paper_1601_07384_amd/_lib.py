@@ -86,7 +86,7 @@ class StepReport(ctypes.Structure):
                 ("first_pressure_seconds", ctypes.c_double),
                 ("first_initial_residual", ctypes.c_double),
                 ("pressure_fused_iter_us", ctypes.c_double),
-                ("guess_weight_network", ctypes.c_double)]
+                ("guess_weight_network", ctypes.c_double), ("status", ctypes.c_int32)]
 
 
 class ModelConfig(ctypes.Structure):

@@ -897,6 +897,7 @@ int viscous_solve(stdg_mesh* m, const double* b, double* x, const stdg_solve_opt
         if (status == STDG_NOT_CONVERGED) break;
         tol *= std::min(0.25, std::max(1e-4, 0.5 * o.rtol / rel));
     }
+    if (status == STDG_OK && rel > o.rtol) status = STDG_NOT_CONVERGED;
     return status;
 }
 
@@ -1007,6 +1008,7 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
             if (status == STDG_NOT_CONVERGED) break;
             tol_abs *= 0.25;
         }
+        if (status == STDG_OK && rel > o.rtol) status = STDG_NOT_CONVERGED;
     } else {
         // FP64 iterative refinement around FP32 Krylov solves
         for (outer = 1; outer <= o.max_outer + 1; ++outer) {

@@ -477,6 +477,8 @@ hipError_t launch_convection(const stdg_mesh* m, const double* vbar, const doubl
     STDG_CV(10, 1) STDG_CV(10, 2) STDG_CV(10, 3) STDG_CV(10, 4) STDG_CV(10, 5)
     STDG_CV(20, 1) STDG_CV(20, 2) STDG_CV(20, 3) STDG_CV(20, 4) STDG_CV(20, 5)
     STDG_CV(35, 1) STDG_CV(35, 2) STDG_CV(35, 3) STDG_CV(35, 4) STDG_CV(35, 5)
+    STDG_CV(56, 1) STDG_CV(56, 2) STDG_CV(56, 3) STDG_CV(56, 4) STDG_CV(56, 5)
+    STDG_CV(84, 1) STDG_CV(84, 2) STDG_CV(84, 3) STDG_CV(84, 4) STDG_CV(84, 5)
 #undef STDG_CV
     return hipErrorInvalidValue;
 }
@@ -683,6 +685,7 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     if (!cm || !vhat || !vbar || !p || !opts) { set_error("null argument"); return STDG_ERR_ARG; }
     stdg_mesh* m = const_cast<stdg_mesh*>(cm);
     if (!m->d.blocks || !m->pd.A) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
+    if (m->G > 5) { set_error("the Picard step is implemented for p_gamma <= 4"); return STDG_ERR_ARG; }
     const int64_t F = (int64_t)m->faces.size(), E = m->E, NI = m->n_interior;
     if (F > NI && !g_nodal) { set_error("Dirichlet data required on a mesh with boundary faces"); return STDG_ERR_ARG; }
     const int npic = opts->n_picard > 0 ? opts->n_picard : m->G;
@@ -783,6 +786,7 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     double guess_w = 0.0;
     double fused_us_sum = 0.0, fused_w = 0.0;
     double pres = 0.0, vres = 0.0, psec = 0.0, vsec = 0.0, first_sec = 0.0, first_res0 = 0.0;
+    int status = STDG_OK;   // STDG_NOT_CONVERGED once a solve stops at its limit
     for (int k = 0; k < npic; ++k) {
         // step 1
         if (int e = stdg_main_from_dual(m, vk, vbk, s)) return e;
@@ -800,6 +804,7 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         auto tv0 = std::chrono::steady_clock::now();
         int e = viscous_solve(m, rhs, vhalf, opts->viscous, kw, s, vit, vrel);
         if (e < 0) return e;
+        if (e == STDG_NOT_CONVERGED) status = STDG_NOT_CONVERGED;
         STDG_HIP(hipStreamSynchronize(s));
         vsec += std::chrono::duration<double>(std::chrono::steady_clock::now() - tv0).count();
         viters += vit;
@@ -842,6 +847,7 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         const double guess_sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - tg0).count();
         e = stdg_pressure_solve(m, bp, dp, &opts->pressure, &prep, s);
         if (e < 0) return e;
+        if (e == STDG_NOT_CONVERGED) status = STDG_NOT_CONVERGED;
         piters += prep.inner_iters;
         papplies += prep.applies;
         fused_us_sum += prep.fused_iter_us * prep.inner_iters;
@@ -885,6 +891,7 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         rep->first_initial_residual = first_res0;
         rep->pressure_fused_iter_us = fused_w > 0.0 ? fused_us_sum / fused_w : 0.0;
         rep->guess_weight_network = guess_w;
+        rep->status = status;
     }
-    return STDG_OK;
+    return status;
 }

@@ -10,8 +10,8 @@ numbering) and main-grid coefficients; the pressure to 1e-8 relative.
 import numpy as np
 import pytest
 
-from stdg_inputs import (kuhn_mesh, node_coordinates, beltrami_velocity, fourier_modes,
-                         fourier_velocity, time_nodes)
+from stdg_inputs import (kuhn_mesh, node_coordinates, node_reference_points, beltrami_velocity,
+                         fourier_modes, fourier_velocity, time_nodes)
 from oracle.mesh import Mesh as OracleMesh
 from oracle.picard import divergence, initial_state, picard_step
 from oracle.pressure import anchor_indices
@@ -56,7 +56,43 @@ def from_dev_dual(t, fmap, F, Nst):
     return out
 
 
+def dual_values(ops, vh):
+    """Values of every dual element's space-time velocity (F, 3, Nst) at the
+    degree-p nodes of its sub-tetrahedra (unisolvent, so two dual fields
+    agree iff these values do).  The Taylor coefficients of eq. bf_2 are not
+    compared directly: the dual mass matrices reach condition numbers near
+    1e9 at p = 4, so FP64 coefficients differ by up to that many ulps while
+    the fields they represent agree to rounding."""
+    ref = np.asarray(node_reference_points(ops.p), np.float64)
+    out = []
+    for j in range(ops.mesh.F):
+        sides = (0, 1) if ops.mesh.right[j] >= 0 else (0,)
+        pts = np.vstack([ops.mesh.subtet(j, s)[:1] + ref @ (ops.mesh.subtet(j, s)[1:] - ops.mesh.subtet(j, s)[:1])
+                         for s in sides])
+        V = ops.dual_basis(j).eval(pts)                                   # longdouble (m, N)
+        c = np.asarray(vh[j], np.longdouble).reshape(3, ops.G, -1)
+        out.append(np.einsum("mk,cgk->mcg", V, c).astype(np.float64).ravel())
+    return np.concatenate(out)
+
+
+def dual_close(ops, a, b, rtol):
+    va, vb = dual_values(ops, a), dual_values(ops, b)
+    err = np.abs(va - vb).max() / np.abs(vb).max()
+    print(f"  dual field relative difference {err:.3e}", flush=True)
+    return err <= rtol
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
 def run_both(n, p, pg, periodic, nu, dt, n_pic, field, viscous_method=None):
+    # unpreconditioned restarted GMRES (the default for p_gamma > 0) needs
+    # more than 20000 iterations for 1e-13 at p = 4; the time-decoupled CG
+    # solves the same system in a few hundred
+    pressure = {"rtol": 1e-13}
+    if p >= 4:
+        pressure["method"] = P.STDG_CG_TIME
     X, T = kuhn_mesh(n)
     om = OracleMesh(X, T, periodic=periodic)
     ops = SpaceTimeOperators(om, p, pg, dt)
@@ -78,14 +114,15 @@ def run_both(n, p, pg, periodic, nu, dt, n_pic, field, viscous_method=None):
     m.dual_from_main(vbar, vhat)
     torch.cuda.synchronize()
     vh0_g = from_dev_dual(vhat, fmap, m.n_face, m.Nst)
-    # dual (Taylor) coefficients are an ill-conditioned representation at p = 3
-    assert np.abs(vh0_g - vh0).max() <= 1e-11 * np.abs(vh0).max()
+    # values through the Taylor dual mass inverses (condition ~3e9 at p = 4,
+    # growing about tenfold per degree) carry that much more FP64 rounding
+    assert dual_close(ops, vh0_g, vh0, 1e-11 if p <= 4 else 1e-10)
     pg_dev = torch.zeros(m.E * m.Nst, dtype=torch.float64, device=DEV)
     gd = to_dev_main(g, perm) if not periodic else None
     visc = {"rtol": 1e-13}
     if viscous_method is not None:
         visc.update(method=viscous_method, restart=30)
-    rep = m.picard_step(vhat, vbar, pg_dev, gd, n_picard=n_pic, pressure={"rtol": 1e-13}, viscous=visc)
+    rep = m.picard_step(vhat, vbar, pg_dev, gd, n_picard=n_pic, pressure=pressure, viscous=visc)
     vh_g = from_dev_dual(vhat, fmap, m.n_face, m.Nst)
     vb_g = from_dev_main(vbar, perm, m.E, m.Nst)
     p_g = np.empty((m.E, m.Nst))
@@ -100,16 +137,22 @@ CASES = [  # n, p, p_gamma, periodic, nu, dt, n_pic, field
     (2, 3, 0, False, 1e-1, 1e-2, 1, "beltrami"),
     (3, 1, 2, True, 1e-3, 5e-3, 3, "fourier"),
     (6, 2, 0, False, 1e-2, 1e-2, 2, "beltrami"),   # 6^3 x 6 unit cube, one step, 2 Picard
+    (1, 4, 1, False, 5e-2, 2e-2, 2, "beltrami"),   # degrees of the convergence tables on one cube
+    (1, 5, 0, False, 1e-1, 1e-2, 1, "beltrami"),
+    (1, 3, 3, False, 1.0, 1e-2, 2, "beltrami"),
+    (1, 1, 4, False, 1.0, 1e-2, 2, "beltrami"),
 ]
 
 
 @pytest.mark.parametrize("n,p,pg,periodic,nu,dt,n_pic,field", CASES)
 def test_picard_step_matches_oracle(n, p, pg, periodic, nu, dt, n_pic, field):
     print(f"picard case n={n} p={p} pg={pg} periodic={periodic}", flush=True)
-    (vh_o, vb_o, p_o), (vh_g, vb_g, p_g), rep, _ = run_both(n, p, pg, periodic, nu, dt, n_pic, field)
-    assert np.abs(vh_g - vh_o).max() <= 1e-9 * np.abs(vh_o).max()
-    assert np.abs(vb_g - vb_o).max() <= 1e-9 * np.abs(vb_o).max()
-    assert np.abs(p_g - p_o).max() <= 1e-8 * np.abs(p_o).max()
+    (vh_o, vb_o, p_o), (vh_g, vb_g, p_g), rep, (ops, _) = run_both(n, p, pg, periodic, nu, dt, n_pic, field)
+    print(f"  vbar {rel(vb_g, vb_o):.3e}  p {rel(p_g, p_o):.3e}  residuals {rep.max_pressure_residual:.2e} "
+          f"{rep.max_viscous_residual:.2e}", flush=True)
+    assert dual_close(ops, vh_g, vh_o, 1e-9)
+    assert rel(vb_g, vb_o) <= 1e-9
+    assert rel(p_g, p_o) <= 1e-8
     assert rep.max_pressure_residual <= 1e-12
 
 
@@ -118,9 +161,9 @@ def test_picard_step_bicgstab_viscous(n, p, pg, periodic, nu, dt, n_pic, field):
     """The same step with the viscous systems solved by preconditioned
     BiCGStab instead of GMRES."""
     print(f"picard bicgstab case n={n} p={p} pg={pg} periodic={periodic}", flush=True)
-    (vh_o, vb_o, p_o), (vh_g, vb_g, p_g), rep, _ = run_both(n, p, pg, periodic, nu, dt, n_pic, field,
-                                                           viscous_method=P.STDG_BICGSTAB)
-    assert np.abs(vh_g - vh_o).max() <= 1e-9 * np.abs(vh_o).max()
+    (vh_o, vb_o, p_o), (vh_g, vb_g, p_g), rep, (ops, _) = run_both(n, p, pg, periodic, nu, dt, n_pic, field,
+                                                                   viscous_method=P.STDG_BICGSTAB)
+    assert dual_close(ops, vh_g, vh_o, 1e-9)
     assert np.abs(vb_g - vb_o).max() <= 1e-9 * np.abs(vb_o).max()
     assert np.abs(p_g - p_o).max() <= 1e-8 * np.abs(p_o).max()
     assert rep.max_viscous_residual <= 1e-12

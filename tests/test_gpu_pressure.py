@@ -41,7 +41,7 @@ def lib_apply(m, x_int, precision=P.STDG_FP64):
 SMALL = [  # n, p, p_gamma, periodic, jitter
     (2, 1, 0, False, 0.0), (2, 2, 0, False, 0.15), (3, 2, 1, True, 0.0),
     (3, 3, 0, False, 0.0), (2, 2, 2, False, 0.1), (3, 1, 3, True, 0.0),
-    (2, 4, 1, False, 0.0)]
+    (2, 4, 1, False, 0.0), (2, 5, 0, False, 0.0)]
 
 
 @pytest.mark.parametrize("n,p,pg,periodic,jitter", SMALL)
@@ -54,7 +54,11 @@ def test_apply_matches_oracle_small(n, p, pg, periodic, jitter):
     yo = apply_S(ops, x)
     perm = m.permutation()
     yg = to_input(lib_apply(m, x[perm]), perm)
-    assert np.abs(yg - yo).max() <= 1e-12 * np.abs(yo).max()
+    # the stored FP64 blocks pass through the Taylor dual mass inverses (eq.
+    # bf_2), whose condition number grows about tenfold per degree (~3e9 at
+    # p = 4); at p = 5 the blocks' own rounding reaches a few 1e-12 of |y|
+    tol = 1e-12 if p <= 4 else 1e-11
+    assert np.abs(yg - yo).max() <= tol * np.abs(yo).max()
 
 
 def test_apply_c1_full_mesh():
