@@ -214,11 +214,23 @@ def _face_psi_mass(ops, j):
 
 
 def picard_step(ops, vhat_prev, vbar_prev, g_nodal, nu, n_pic, anchor_elem=0, anchor_node=0,
-                p_init=None):
+                p_init=None, theta=1.0, p_prev=None):
     """One time step.  Returns (vhat, vbar_new, p, diagnostics).
 
     p_init: pressure guess p^{n+1,0} (E, Nst); zero (the paper's choice) when
-    None, or e.g. the previous slab's pressure (the paper's alternative)."""
+    None, or e.g. the previous slab's pressure (the paper's alternative).
+
+    theta: implicitness of the pressure for p_gamma = 0 (Sec. 2.7, eqs.
+    CS_15_theta and CS_16_theta): the momentum equation carries
+    theta p^{n+1} + (1 - theta) p^n, p^n = p_prev.  In this pressure-correction
+    form that pressure enters Lambda, the correction system becomes
+    theta S dp = b, and the dual velocity is corrected by theta M^-1 Q dp.
+    theta = 1 is the scheme of Sec. 2.6."""
+    if theta != 1.0:
+        if ops.G != 1:
+            raise ValueError("the theta-method is defined for p_gamma = 0")
+        if p_prev is None:
+            raise ValueError("theta < 1 needs the previous pressure p_prev")
     mesh = ops.mesh
     E, Fn, Nst = mesh.E, mesh.F, ops.Nst
     bfaces = [j for j in range(Fn) if mesh.right[j] < 0]
@@ -248,7 +260,8 @@ def picard_step(ops, vhat_prev, vbar_prev, g_nodal, nu, n_pic, anchor_elem=0, an
     for k in range(n_pic):
         # step 1
         vbar_k = average(ops, vhat)
-        lam = prev_pressure(ops, p)
+        p_mom = p if theta == 1.0 else theta * p + (1.0 - theta) * linalg.asreal(p_prev)
+        lam = prev_pressure(ops, p_mom)
         # step 2
         ups = convection(ops, vbar_k, vhat_bc)
         # step 3
@@ -272,14 +285,14 @@ def picard_step(ops, vhat_prev, vbar_prev, g_nodal, nu, n_pic, anchor_elem=0, an
             F = ops.face(j)
             for s in F["sides"]:
                 b[F[("elem", s)]] -= np.einsum("dkl,dl->k", F[("D", s)], Fv[j])
-        dp = solve_anchored(ops, S, b.astype(np.float64).ravel(), anchor_elem, anchor_node)
+        dp = solve_anchored(ops, theta * S, b.astype(np.float64).ravel(), anchor_elem, anchor_node)
         dp = linalg.asreal(dp).reshape(E, Nst)
         diag["solves"].append({"b": b.astype(np.float64), "dp": dp.astype(np.float64)})
         # step 6
         for j in ifaces:
             F = ops.face(j)
             g = sum(np.einsum("dkl,l->dk", F[("Q", s)], dp[F[("elem", s)]]) for s in (0, 1))
-            vhat[j] = Fv[j] - linalg.solve(F["M"], g.T).T
+            vhat[j] = Fv[j] - theta * linalg.solve(F["M"], g.T).T
         for j in bfaces:
             vhat[j] = vhat_bc[j]
         p = p + dp

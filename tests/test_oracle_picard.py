@@ -11,6 +11,12 @@
   the anchor.
 * Corollaries 3-4: the viscous system is symmetric positive definite for
   p_gamma = 0.
+* theta-method (Sec. 2.7, eqs. CS_15_theta-CS_16_theta): with the
+  previous pressure p^n = q the same steady linear flow is returned for
+  theta = 1/2 and 3/4 (a dropped (1 - theta) p^n term returns q / theta);
+  the step stays divergence-free (a correction not scaled by theta breaks
+  eq. CS_15_theta); and with pi = theta p + (1 - theta) p^n the step is the
+  theta = 1 step in pi started from theta p^{n+1,0} + (1 - theta) p^n.
 * Convection of a continuous polynomial field equals int phi~ div(u (x) u)
   (Green's formula; the Rusanov jump is zero), and for piecewise-constant
   states only face terms remain: sum_f int phi (F^RS - F(v_i)).n.
@@ -43,7 +49,7 @@ def _nodal_scalar(ops, fn):
     return np.tile(fn(xn), (1, ops.G))
 
 
-def _run_linear(pg, nu, use_exact_guess):
+def _run_linear(pg, nu, use_exact_guess, theta=1.0):
     X, T = kuhn_mesh(2)
     ops = SpaceTimeOperators(Mesh(X, T), 2, pg, 0.05)
     u = _nodal_field(ops, lambda x: x @ A.T)
@@ -52,7 +58,8 @@ def _run_linear(pg, nu, use_exact_guess):
     q = q - q.ravel()[idx[0]]                           # anchored at node 0 of element 0
     vhat0 = initial_state(ops, u)
     vhat, vbar, p, _ = picard_step(ops, vhat0, u, u, nu, pg + 1,
-                                   p_init=q if use_exact_guess else None)
+                                   p_init=q if use_exact_guess else None, theta=theta,
+                                   p_prev=q if theta != 1.0 else None)
     return vhat, vbar, p, vhat0, u, q
 
 
@@ -87,6 +94,47 @@ def test_divergence_free_after_step(periodic, pg):
     scale = np.abs(divergence(ops, initial_state(ops, u))).max() + 1e-30
     div[0] = 0.0                      # the anchor element absorbs the compatibility defect
     assert np.abs(div).max() <= 1e-10 * max(scale, np.abs(vhat).max() * 0.1)
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.75])
+@pytest.mark.parametrize("nu,exact_guess", [(0.0, False), (0.05, True)])
+def test_theta_method_keeps_the_steady_linear_flow(theta, nu, exact_guess):
+    vhat, vbar, p, vhat0, u, q = _run_linear(0, nu, exact_guess, theta=theta)
+    assert np.abs(vhat - vhat0).max() <= 1e-11 * np.abs(vhat0).max()
+    assert np.abs(vbar - u).max() <= 1e-11 * np.abs(u).max()
+    assert np.abs(p - q).max() <= 1e-10 * np.abs(q).max()
+
+
+def _theta_case():
+    X, T = kuhn_mesh(2)
+    ops = SpaceTimeOperators(Mesh(X, T), 1, 0, 0.02)
+    u = _nodal_field(ops, lambda x: beltrami_velocity(x))
+    rng = np.random.default_rng(11)
+    p_prev = rng.standard_normal((ops.mesh.E, ops.Nst))
+    p_prev -= p_prev.ravel()[anchor_indices(ops)[0]]
+    return ops, u, p_prev
+
+
+def test_theta_method_divergence_free():
+    ops, u, p_prev = _theta_case()
+    vhat, _, _, _ = picard_step(ops, initial_state(ops, u), u, u, 0.01, 2, theta=0.5, p_prev=p_prev)
+    div = divergence(ops, vhat)
+    div[0] = 0.0
+    assert np.abs(div).max() <= 1e-10 * np.abs(vhat).max()
+
+
+@pytest.mark.parametrize("guess", ["zero", "previous"])
+def test_theta_method_is_the_plain_step_in_the_weighted_pressure(guess):
+    ops, u, p_prev = _theta_case()
+    theta = 0.6
+    p0 = None if guess == "zero" else p_prev
+    vh_t, vb_t, p_t, _ = picard_step(ops, initial_state(ops, u), u, u, 0.01, 2, p_init=p0,
+                                     theta=theta, p_prev=p_prev)
+    pi0 = (1.0 - theta) * p_prev + (0.0 if p0 is None else theta * p0)
+    vh_1, vb_1, pi, _ = picard_step(ops, initial_state(ops, u), u, u, 0.01, 2, p_init=pi0)
+    assert np.abs(vh_t - vh_1).max() <= 1e-12 * np.abs(vh_1).max()
+    assert np.abs(vb_t - vb_1).max() <= 1e-12 * np.abs(vb_1).max()
+    assert np.abs(theta * p_t + (1.0 - theta) * p_prev - pi).max() <= 1e-11 * np.abs(pi).max()
 
 
 def test_viscous_system_spd_for_piecewise_constant_time():
