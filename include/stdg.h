@@ -258,6 +258,16 @@ typedef struct {
                                 /* right-hand side of the first pressure solve */
     double* rec_x;              /* device [E][G][N] or NULL: receives         */
                                 /* p^{n+1,1} (training data for the model)    */
+    double theta;               /* implicitness of the pressure in the        */
+                                /* momentum equation, p_gamma = 0 only (Sec.  */
+                                /* 2.7, eqs. CS_15_theta/CS_16_theta): the    */
+                                /* step carries theta p^{n+1} + (1-theta) p^n */
+                                /* in [1/2, 1]; 1 (default) is the scheme of  */
+                                /* Sec. 2.6, 1/2 Crank-Nicolson.  With theta  */
+                                /* < 1, p must hold p^n on entry, and hist,   */
+                                /* rec_x and the solves work on the weighted  */
+                                /* pressure; out of range or with p_gamma > 0 */
+                                /* the step returns STDG_ERR_ARG              */
 } stdg_step_opts;
 
 typedef struct {

@@ -48,7 +48,7 @@ def solve_opts(**kw):
 
 
 def step_opts(n_picard=0, pressure_guess=0, pressure=None, viscous=None, krylov_guess=0,
-              model=None, hist=None, rec_b=None, rec_x=None):
+              model=None, hist=None, rec_b=None, rec_x=None, theta=1.0):
     """Step options; tensors given here must stay alive until the step returns."""
     o = StepOpts()
     _lib.load().stdg_step_opts_default(ctypes.byref(o))
@@ -60,6 +60,7 @@ def step_opts(n_picard=0, pressure_guess=0, pressure=None, viscous=None, krylov_
                 raise TypeError(f"unknown {name} option {k}")
             setattr(getattr(o, name), k, v)
     o.krylov_guess = krylov_guess
+    o.theta = theta
     o.model = model._h.value if model is not None else None
     for name, t in (("hist", hist), ("rec_b", rec_b), ("rec_x", rec_x)):
         setattr(o, name, t.data_ptr() if t is not None else None)

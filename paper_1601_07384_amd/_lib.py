@@ -74,7 +74,7 @@ class StepOpts(ctypes.Structure):
                 ("pressure", SolveOpts), ("viscous", SolveOpts),
                 ("krylov_guess", ctypes.c_int32), ("model", ctypes.c_void_p),
                 ("hist", ctypes.c_void_p), ("rec_b", ctypes.c_void_p),
-                ("rec_x", ctypes.c_void_p)]
+                ("rec_x", ctypes.c_void_p), ("theta", ctypes.c_double)]
 
 
 class StepReport(ctypes.Structure):

@@ -196,6 +196,12 @@ __global__ void k_copyd(const double* __restrict__ x, double* __restrict__ y, in
     if (t < n) y[t] = x[t];
 }
 
+// p <- (pi - (1 - theta) p) / theta: the end-of-step pressure of the theta-method
+__global__ void k_theta_end(const double* __restrict__ pi, double* __restrict__ p, double theta, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (pi[i] - (1.0 - theta) * p[i]) / theta;
+}
+
 __global__ void k_zero(double* __restrict__ y, int64_t n) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) y[t] = 0.0;
@@ -648,6 +654,7 @@ extern "C" void stdg_step_opts_default(stdg_step_opts* o) {
     o->hist = nullptr;
     o->rec_b = nullptr;
     o->rec_x = nullptr;
+    o->theta = 1.0;
 }
 
 extern "C" int stdg_dual_from_main(const stdg_mesh* m, const double* vbar, double* vhat, void* stream) {
@@ -686,6 +693,9 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     stdg_mesh* m = const_cast<stdg_mesh*>(cm);
     if (!m->d.blocks || !m->pd.A) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
     if (m->G > 5) { set_error("the Picard step is implemented for p_gamma <= 4"); return STDG_ERR_ARG; }
+    const double theta = opts->theta;
+    if (!(theta >= 0.5 && theta <= 1.0)) { set_error("theta must lie in [1/2, 1]"); return STDG_ERR_ARG; }
+    if (theta != 1.0 && m->G != 1) { set_error("the theta-method is defined for p_gamma = 0"); return STDG_ERR_ARG; }
     const int64_t F = (int64_t)m->faces.size(), E = m->E, NI = m->n_interior;
     if (F > NI && !g_nodal) { set_error("Dirichlet data required on a mesh with boundary faces"); return STDG_ERR_ARG; }
     const int npic = opts->n_picard > 0 ? opts->n_picard : m->G;
@@ -777,10 +787,16 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
                                vbc + ((int64_t)c * F + NI) * G * N, vk + ((int64_t)c * F + NI) * G * N,
                                (F - NI) * G * N);
     }
-    if (opts->pressure_guess == STDG_GUESS_PREVIOUS)
+    // pk holds the pressure that the momentum equation carries: p^{n+1,k}, or
+    // for the theta-method pi = theta p^{n+1,k} + (1 - theta) p^n, which makes
+    // every later stage the theta = 1 step in pi (corrections of pi are theta
+    // times those of p^{n+1}, with the same anchor)
+    if (opts->pressure_guess == STDG_GUESS_PREVIOUS) {
         hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, p, pk, nP);
-    else
+    } else {
         hipLaunchKernelGGL(k_zero, dim3(nblk(nP)), dim3(256), 0, s, pk, nP);
+        if (theta != 1.0) hipLaunchKernelGGL(k_axpy, dim3(nblk(nP)), dim3(256), 0, s, pk, p, 1.0 - theta, nP);
+    }
     STDG_HIP(hipGetLastError());
     int piters = 0, viters = 0, papplies = 0, first_iters = 0;
     double guess_w = 0.0;
@@ -874,7 +890,10 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
         STDG_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_copyd, dim3(nblk(nD)), dim3(256), 0, s, vk, vhat, nD);
-    hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, pk, p, nP);
+    if (theta == 1.0)
+        hipLaunchKernelGGL(k_copyd, dim3(nblk(nP)), dim3(256), 0, s, pk, p, nP);
+    else    // p^{n+1} = (pi - (1 - theta) p^n) / theta
+        hipLaunchKernelGGL(k_theta_end, dim3(nblk(nP)), dim3(256), 0, s, pk, p, theta, nP);
     if (int e = stdg_main_from_dual(m, vk, vbar, s)) return e;
     STDG_HIP(hipStreamSynchronize(s));
     if (rep) {

@@ -60,7 +60,7 @@ def l2_errors(X, T, p, pres, vel, t, nu):
     return ep, ev
 
 
-def run_abc(n, p, pg, nu, t_end=0.1, cfl=0.3):
+def run_abc(n, p, pg, nu, t_end=0.1, cfl=0.3, theta=1.0, exact_p0=False):
     X, T = kuhn_mesh(n, lo=LO, hi=HI)
     h = (HI[0] - LO[0]) / n
     vmax = 2.0 * math.sqrt(3.0)
@@ -76,7 +76,10 @@ def run_abc(n, p, pg, nu, t_end=0.1, cfl=0.3):
     vhat = torch.empty(3 * m.n_face * m.Nst, dtype=torch.float64, device=DEV)
     m.dual_from_main(vbar, vhat)
     pr = torch.zeros(E * m.Nst, dtype=torch.float64, device=DEV)
-    opts = P.step_opts(pressure_guess=P.STDG_GUESS_PREVIOUS,
+    if exact_p0:            # p^0 at the nodes (the theta-method reads p^n)
+        p0 = np.repeat(beltrami_pressure(xn, 0.0, nu)[perm][:, None, :], G, axis=1)
+        pr.copy_(torch.tensor(p0.ravel(), dtype=torch.float64))
+    opts = P.step_opts(pressure_guess=P.STDG_GUESS_PREVIOUS, theta=theta,
                        pressure={"method": P.STDG_CG_TIME, "precision": P.STDG_FP32, "rtol": 1e-10,
                                  "inner_rtol": 1e-5, "max_iter": 200000},
                        viscous={"method": P.STDG_BICGSTAB, "restart": 30, "rtol": 1e-12, "check_every": 1})
@@ -135,3 +138,20 @@ def test_steady_abc_matches_table1(p):
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_unsteady_abc_matches_table2(p):
     check_against_table("abc_unsteady_table2.json", p, p, 1.0)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_crank_nicolson_on_unsteady_abc(p):
+    """theta-method (Sec. 2.7, eq. CS_16_theta) at scale: unsteady ABC flow
+    (nu = 1, p_gamma = 0) on 6^3 x 6 elements, theta = 1/2 against theta = 1,
+    starting from the exact p^0.  Only the pressure is weighted, so the
+    velocity errors agree to a few percent; the pressure errors stay of the
+    same size (the paper's gain in time is not resolved at these sizes: the
+    measured ratio ranges 0.18-1.15)."""
+    for cfl in (0.3, 0.15):
+        (ep1, ev1), steps = run_abc(6, p, 0, 1.0, cfl=cfl, theta=1.0, exact_p0=True)
+        (eph, evh), _ = run_abc(6, p, 0, 1.0, cfl=cfl, theta=0.5, exact_p0=True)
+        print(f"p={p} cfl={cfl} steps={steps}: theta 1: err_p {ep1:.4e} err_v {ev1:.4e}; "
+              f"theta 1/2: err_p {eph:.4e} err_v {evh:.4e}", flush=True)
+        assert abs(evh - ev1) <= 0.05 * ev1
+        assert eph <= 1.5 * ep1

@@ -202,3 +202,52 @@ def test_steady_linear_flow_c1_mesh():
     pr = np.empty_like(q)
     pr[perm] = pd.cpu().numpy().reshape(q.shape)
     assert np.abs(pr - q).max() <= 1e-9 * np.abs(q).max()
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.75])
+@pytest.mark.parametrize("guess", ["zero", "previous"])
+def test_theta_method_matches_oracle(theta, guess):
+    """theta-method for p_gamma = 0 (Sec. 2.7, eqs. CS_15_theta-CS_16_theta):
+    the library solves for the weighted pressure and recovers p^{n+1} at the
+    end; the oracle takes the literal theta S dp = b form."""
+    print(f"theta case theta={theta} guess={guess}", flush=True)
+    n, p, nu, dt, n_pic = 2, 2, 1e-2, 1e-2, 2
+    X, T = kuhn_mesh(n)
+    om = OracleMesh(X, T)
+    ops = SpaceTimeOperators(om, p, 0, dt)
+    fn = lambda x, t: beltrami_velocity(x, t, nu)
+    u0 = nodal(X, T, p, 1, lambda x, t: fn(x, 0.0))
+    g = nodal(X, T, p, 1, fn, 0.0, dt)
+    p_prev = np.random.default_rng(5).standard_normal((om.E, ops.Nst))
+    vh0 = initial_state(ops, u0)
+    vh_o, vb_o, p_o, _ = picard_step(ops, vh0, u0, g, nu, n_pic, theta=theta, p_prev=p_prev,
+                                     p_init=p_prev if guess == "previous" else None)
+    m = P.Mesh(X, T, p, 0, dt=dt, nu=nu)
+    perm = m.permutation()
+    fmap = face_map(m, om, perm)
+    vbar = to_dev_main(u0, perm)
+    vhat = torch.empty(3 * m.n_face * m.Nst, dtype=torch.float64, device=DEV)
+    m.dual_from_main(vbar, vhat)
+    pd = torch.tensor(np.ascontiguousarray(p_prev[perm]).ravel(), dtype=torch.float64, device=DEV)
+    opts = P.step_opts(n_picard=n_pic, theta=theta, pressure={"rtol": 1e-13}, viscous={"rtol": 1e-13},
+                       pressure_guess=P.STDG_GUESS_PREVIOUS if guess == "previous" else P.STDG_GUESS_ZERO)
+    rep = m.picard_step(vhat, vbar, pd, to_dev_main(g, perm), opts=opts)
+    vh_g = from_dev_dual(vhat, fmap, m.n_face, m.Nst)
+    vb_g = from_dev_main(vbar, perm, m.E, m.Nst)
+    p_g = np.empty((m.E, m.Nst))
+    p_g[perm] = pd.cpu().numpy().reshape(m.E, m.Nst)
+    print(f"  vbar {rel(vb_g, vb_o):.3e}  p {rel(p_g, p_o):.3e}", flush=True)
+    assert rep.status == P.STDG_OK
+    assert dual_close(ops, vh_g, vh_o, 1e-9)
+    assert rel(vb_g, vb_o) <= 1e-9
+    assert rel(p_g, p_o) <= 1e-8
+
+
+def test_theta_method_rejected_for_space_time_pressure():
+    X, T = kuhn_mesh(2)
+    m = P.Mesh(X, T, 1, 1, dt=1e-2, nu=1e-2)
+    vbar = torch.zeros(3 * m.E * m.Nst, dtype=torch.float64, device=DEV)
+    vhat = torch.zeros(3 * m.n_face * m.Nst, dtype=torch.float64, device=DEV)
+    pd = torch.zeros(m.E * m.Nst, dtype=torch.float64, device=DEV)
+    with pytest.raises(P.StdgError):
+        m.picard_step(vhat, vbar, pd, vbar, opts=P.step_opts(theta=0.5))
