@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--record", type=int, default=12, help="steps recorded to train the learned guess")
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--lr", type=float, default=3e-4)
+    ap.add_argument("--jitter", type=float, default=0.0,
+                    help="move interior vertices by up to this fraction of h: every element then "
+                         "has its own geometry class (operator blocks streamed per element)")
     return ap.parse_args()
 
 
@@ -109,7 +112,7 @@ def main():
     import paper_1601_07384_amd as P
     from stdg_inputs import kuhn_mesh, node_coordinates, fourier_modes, fourier_velocity
 
-    X, T = kuhn_mesh(N_HEX)
+    X, T = kuhn_mesh(N_HEX, jitter=args.jitter, seed=7)
     t0 = time.perf_counter()
     m = P.Mesh(X, T, P_DEG, P_GAMMA, dt=DT, nu=NU, periodic=True)
     build_s = time.perf_counter() - t0
@@ -215,11 +218,13 @@ def main():
     k_us = ev0.elapsed_time(ev1) * 1e3 / args.applies
     dofs = E * Nst
     flops = 2.0 * N * N * G * 5 * E + 2.0 * N * G * G * E          # 5 N x N blocks x G columns + time mix
-    bytes_alg = 2.0 * dofs * 8 + 20.0 * E                           # x and y once, 5 int32 indices
+    # x and y once, 5 int32 indices, the five N x N blocks of every geometry class once
+    bytes_alg = 2.0 * dofs * 8 + 20.0 * E + 8.0 * 5 * N * N * m.n_classes
     # one-kernel FP32 CG iteration (B (x) I): r, p, q, x read and written once
     it_us = sum(r.pressure_fused_iter_us * r.pressure_iters for r in reps) / max(
         sum(r.pressure_iters for r in reps if r.pressure_fused_iter_us > 0), 1)
-    k_bytes = 8.0 * dofs * 4 + 20.0 * E
+    # ... and the five blocks and the block-Jacobi inverse of every class once
+    k_bytes = 8.0 * dofs * 4 + 20.0 * E + 4.0 * 6 * N * N * m.n_classes
     k_flops = 2.0 * N * N * 5 * E * G
     k_s = it_us * 1e-6 if it_us > 0 else float("nan")
 
@@ -249,8 +254,10 @@ def main():
         "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": "periodic unit cube, 24^3 hexahedra x 6 = 82,944 tets, p=3, "
                                "p_gamma=1 (40 DoF/tet), nu=1e-3, dt=1e-3, 2 Picard iterations "
-                               "per step, 16 seeded Fourier modes",
-                   "pressure_dof": dofs},
+                               "per step, 16 seeded Fourier modes"
+                               + (f", interior vertices jittered by up to {args.jitter} h"
+                                  if args.jitter else ""),
+                   "pressure_dof": dofs, "geometry_classes": m.n_classes},
         "step": {"pressure_s": first.pressure_seconds, "viscous_s": first.viscous_seconds,
                  "pressure_iters": first.pressure_iters, "viscous_iters": first.viscous_iters,
                  "pressure_applies": first.pressure_applies,
@@ -270,7 +277,7 @@ def main():
                               "hbm_gbs_algorithmic": bytes_alg / t_apply / 1e9},
         "roofline": {"bound": "hbm", "achieved": k_bytes / k_s / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": k_bytes / k_s / 1e9 / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if N == 20 else None,
+                     "traffic": measured_traffic() if N == 20 and args.jitter == 0 else None,
                      "kernel": f"k_cg_op<{N},true> (+ k_cg_red, one CG iteration)", "kernel_us": it_us,
                      "kernel_launches": sum(r.pressure_iters for r in reps),
                      "plain_operator_kernel": {"kernel": f"k_cg_op<{N},false>", "us": k_us,

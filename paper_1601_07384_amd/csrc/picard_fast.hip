@@ -286,8 +286,11 @@ hipError_t blockdiag_ng(const stdg_mesh* m, const double* x, double* y, hipStrea
 // column.  The per-time-point sums go to tmp[t][3][E][N]
 // and kf_conv_combine weights them with the time basis (fixed order).  A
 // wavefront that mixes classes (the tail of a mesh with many classes) runs
-// the classes present one after the other, the other lanes masked.
-template <int N, int G>
+// the classes present one after the other, the other lanes masked.  With
+// MIXED (meshes whose classes hold fewer elements than a wavefront, e.g.
+// unstructured ones where every element is its own class) each lane reads
+// its own class's tables with vector loads in a single pass.
+template <int N, int G, bool MIXED>
 __global__ void __launch_bounds__(64) kf_convection(
     const double* __restrict__ vbar, const double* __restrict__ vbc, const int32_t* __restrict__ cls,
     const int32_t* __restrict__ nbr, const int64_t* __restrict__ tet_face, const double* __restrict__ cJinv,
@@ -331,9 +334,9 @@ __global__ void __launch_bounds__(64) kf_convection(
 #pragma unroll
             for (int kk = 0; kk < KH; ++kk) o[cc][kk] = 0.0;
         for (uint64_t todo = __ballot(valid); todo;) {
-            const int cur = __builtin_amdgcn_readlane(c, __builtin_ctzll(todo));
+            const int cur = MIXED ? c : __builtin_amdgcn_readlane(c, __builtin_ctzll(todo));
             const bool mine = valid && c == cur;
-            todo &= ~__ballot(mine);
+            todo = MIXED ? 0 : todo & ~__ballot(mine);
             if (!mine) continue;
             const double* Ji = cJinv + (int64_t)cur * 9;
             const double det = cdet[cur];
@@ -382,12 +385,14 @@ __global__ void __launch_bounds__(64) kf_convection(
                         for (int b = 0; b < G; ++b) s += gt[b] * xp[cc * cstr + b * N + n];
                         xn_s[(cc * N + n) * 64 + lane] = s;
                     }
-                const double* nr = cnrm + __builtin_amdgcn_readfirstlane(cur * 12 + f * 3);
+                const double* nr = cnrm + (MIXED ? cur * 12 + f * 3 : __builtin_amdgcn_readfirstlane(cur * 12 + f * 3));
                 const double n0 = nr[0], n1 = nr[1], n2 = nr[2];
 #pragma unroll 1
                 for (int q = 0; q < nqf; ++q) {
-                    // (wavefront-uniform: the tables are read through the scalar cache)
-                    const int off = __builtin_amdgcn_readfirstlane((cur * 4 + f) * nqf + q);
+                    // (wavefront-uniform unless MIXED: the tables are then read
+                    // through the scalar cache)
+                    const int off = MIXED ? (cur * 4 + f) * nqf + q
+                                          : __builtin_amdgcn_readfirstlane((cur * 4 + f) * nqf + q);
                     const double* pf = PHf + (int64_t)off * N;
                     const double* pn = PHn + (int64_t)off * N;
                     // the neighbour's coefficients are re-read from LDS at every
@@ -471,9 +476,15 @@ hipError_t convection_ng(const stdg_mesh* m, const double* vbar, const double* v
         d.conv_len = need;
     }
     const unsigned blocks = (unsigned)(((m->E + 63) / 64) * t.qt);
-    hipLaunchKernelGGL((kf_convection<N, G>), dim3(blocks), dim3(64), 0, s, vbar, vbc, m->d.cls, m->d.nbr,
-                       d.tet_face, d.cJinv, d.cdet, d.cnrm, d.PHf, d.PHn, d.FW, d.PHv, d.dPHv, d.wv, d.tw, d.gq,
-                       t.nqv, t.nqf, t.qt, d.conv_tmp, m->E, (int64_t)m->faces.size());
+    // per-lane tables once classes average fewer elements than a wavefront
+    if ((int64_t)m->n_classes * 64 > m->E)
+        hipLaunchKernelGGL((kf_convection<N, G, true>), dim3(blocks), dim3(64), 0, s, vbar, vbc, m->d.cls, m->d.nbr,
+                           d.tet_face, d.cJinv, d.cdet, d.cnrm, d.PHf, d.PHn, d.FW, d.PHv, d.dPHv, d.wv, d.tw,
+                           d.gq, t.nqv, t.nqf, t.qt, d.conv_tmp, m->E, (int64_t)m->faces.size());
+    else
+        hipLaunchKernelGGL((kf_convection<N, G, false>), dim3(blocks), dim3(64), 0, s, vbar, vbc, m->d.cls,
+                           m->d.nbr, d.tet_face, d.cJinv, d.cdet, d.cnrm, d.PHf, d.PHn, d.FW, d.PHv, d.dPHv, d.wv,
+                           d.tw, d.gq, t.nqv, t.nqf, t.qt, d.conv_tmp, m->E, (int64_t)m->faces.size());
     const int64_t n = 3 * m->E * N;
     hipLaunchKernelGGL((kf_conv_combine<N, G>), dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256),
                        0, s, d.conv_tmp, d.gq, t.qt, m->cfg.dt, ups, m->E);
