@@ -248,11 +248,17 @@ __global__ void __launch_bounds__(256) k_visc_tn(
     const double* __restrict__ SVt, const double* __restrict__ MIt, const int32_t* __restrict__ cls,
     const int32_t* __restrict__ nbr, const double* __restrict__ Tm, const double* __restrict__ W, double nu_dt,
     const double* __restrict__ x, double* __restrict__ y, int64_t E) {
+    // the 3 G (component, time node) workgroups of one 256-element tile are
+    // consecutive on one XCD (workgroups go round-robin over the 8 XCDs), so
+    // a tile's blocks are re-read from cache while still resident
     const int64_t nbE = (E + 255) / 256;
-    const int a = (int)(blockIdx.x % G);
-    const int64_t rest = blockIdx.x / G;
-    const int comp = (int)(rest / nbE);
-    const int64_t i = (rest % nbE) * 256 + threadIdx.x;
+    const int64_t j = blockIdx.x >> 3;
+    const int v = (int)(j % (3 * G));
+    const int64_t tile = (j / (3 * G)) * 8 + (blockIdx.x & 7);
+    if (tile >= nbE) return;
+    const int a = v % G;
+    const int comp = v / G;
+    const int64_t i = tile * 256 + threadIdx.x;
     const bool valid = i < E;
     const int64_t ii = valid ? i : E - 1;
     const int c = cls[ii];
@@ -549,7 +555,7 @@ hipError_t run_visc_rhs(const stdg_mesh* m, const double* vprev, const double* u
 template <int N, int G>
 static hipError_t launch_visc_ng(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
     const PicardDevice& d = m->pd;
-    const int64_t blocks = (m->E + 255) / 256 * G * 3;
+    const int64_t blocks = ((m->E + 255) / 256 + 7) / 8 * 8 * G * 3;
     hipLaunchKernelGGL((k_visc_tn<N, G>), dim3((unsigned)blocks), dim3(256), 0, s, d.SVt, d.MIt, m->d.cls,
                        m->d.nbr, d.Tm, d.W, m->cfg.nu * m->cfg.dt, x, y, m->E);
     return hipGetLastError();
