@@ -170,6 +170,8 @@ SOLVE = [  # n, p, pg, periodic, jitter, method, precision
     (6, 2, 0, False, 0.0, P.STDG_CG_TIME, P.STDG_FP64),   # reduces to CG when p_gamma = 0
     (3, 2, 1, False, 0.1, P.STDG_BICGSTAB, P.STDG_FP64),
     (3, 2, 1, True, 0.0, P.STDG_BICGSTAB, P.STDG_FP32),
+    (3, 2, 1, True, 0.1, P.STDG_CG_TIME, P.STDG_FP32),   # fused FP32 PCG, every tile mixing classes
+    (3, 3, 0, True, 0.1, P.STDG_CG, P.STDG_FP32),
 ]
 
 
