@@ -512,6 +512,18 @@ int cg(Ctx& c, const T* b, T* x, T* r, T* p, T* q, double tol_abs, int max_it, i
     const int gb = grid_for(n);
     CK(Apply<T>::run(c, x, q)); c.applies++;
     hipLaunchKernelGGL((k_resid<T, T>), dim3(NBLK), dim3(RT), 0, c.s, b, q, r, n, c.partial);
+    if constexpr (std::is_same<T, double>::value) {
+        if (c.op == 0 || c.op == 2) {
+            // the starting residual projected on the range of the pressure
+            // operator (per-time-node mean removed): near the FP64 floor the
+            // rounding of b - S x leaves a part along the null space that CG
+            // cannot reduce and would amplify
+            if (int e = time_sums(c, r)) return e;
+            hipLaunchKernelGGL(k_remove_mean<double>, dim3(gb), dim3(256), 0, c.s, r, c.scal + S_TIME, c.m->E,
+                               c.m->G, c.m->N);
+            hipLaunchKernelGGL((k_dot<double, double>), dim3(NBLK), dim3(RT), 0, c.s, r, r, n, c.partial);
+        }
+    }
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_RR, (int)FIN_STORE);
     hipLaunchKernelGGL(k_copy<T>, dim3(gb), dim3(256), 0, c.s, r, p, n);
     CK(hipGetLastError());
