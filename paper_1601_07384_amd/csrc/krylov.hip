@@ -727,6 +727,15 @@ int bicgstab(Ctx& c, const T* b, T* x, T* r, T* rh, T* p, T* v, T* s, T* t, doub
     const int gb = grid_for(n);
     CK(Apply<T>::run(c, x, v)); c.applies++;
     hipLaunchKernelGGL((k_resid<T, T>), dim3(NBLK), dim3(RT), 0, c.s, b, v, r, n, c.partial);
+    if constexpr (std::is_same<T, double>::value) {
+        if (c.op == 0 || c.op == 2) {
+            // starting residual on the range of the pressure operator (as in cg())
+            if (int e = time_sums(c, r)) return e;
+            hipLaunchKernelGGL(k_remove_mean<double>, dim3(gb), dim3(256), 0, c.s, r, c.scal + S_TIME, c.m->E,
+                               c.m->G, c.m->N);
+            hipLaunchKernelGGL((k_dot<double, double>), dim3(NBLK), dim3(RT), 0, c.s, r, r, n, c.partial);
+        }
+    }
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, c.s, c.partial, NBLK, c.scal, (int)S_BRR, (int)FIN_STORE);
     hipLaunchKernelGGL(k_copy<T>, dim3(gb), dim3(256), 0, c.s, r, rh, n);
     hipLaunchKernelGGL(k_fill<T>, dim3(gb), dim3(256), 0, c.s, p, (T)0, n);
