@@ -205,7 +205,9 @@ void stdg_solve_opts_default(stdg_solve_opts* opts);
  * and the solution (with x_anchor = 0) on exit.  The library solves the
  * equivalent consistent singular system S x = b~ and shifts by a constant per
  * time node.  Synchronises `stream` before returning.  Returns STDG_OK,
- * STDG_NOT_CONVERGED (x = last iterate) or an error. */
+ * STDG_NOT_CONVERGED (x = last iterate; also when rtol lies below what FP64
+ * rounding of the system allows, the solve then stopping near that floor)
+ * or an error. */
 int stdg_pressure_solve(const stdg_mesh* mesh, const double* b, double* x,
                         const stdg_solve_opts* opts, stdg_solve_report* report,
                         void* stream);
