@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <numeric>
 
 namespace stdg {
@@ -103,7 +105,24 @@ static void jacobi01(int n, real alpha, std::vector<real>& x, std::vector<real>&
     }
 }
 
-Rule tet_rule(int q) {
+// The rules depend only on q and cost an eigen-decomposition per direction;
+// the block precompute asks for the same few rules for every face of every
+// geometry class, so each is built once per process and then copied.
+// (std::map entries never move and are never erased, so the references
+// handed out stay valid while other threads add rules)
+template <typename Build>
+static const Rule& cached_rule(std::map<int, Rule>& cache, std::mutex& mu, int q, Build build) {
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        const auto it = cache.find(q);
+        if (it != cache.end()) return it->second;
+    }
+    Rule r = build(q);
+    std::lock_guard<std::mutex> lk(mu);
+    return cache.emplace(q, std::move(r)).first->second;
+}
+
+static Rule build_tet_rule(int q) {
     std::vector<real> xu, wu, xv, wv, xw, ww;
     jacobi01(q, 2.0, xu, wu);
     jacobi01(q, 1.0, xv, wv);
@@ -119,7 +138,7 @@ Rule tet_rule(int q) {
     return r;
 }
 
-Rule tri_rule(int q) {
+static Rule build_tri_rule(int q) {
     std::vector<real> xu, wu, xv, wv;
     jacobi01(q, 1.0, xu, wu);
     gauss_legendre01(q, xv, wv);
@@ -130,6 +149,18 @@ Rule tri_rule(int q) {
             r.w.push_back(wu[i] * wv[j]);
         }
     return r;
+}
+
+const Rule& tet_rule(int q) {
+    static std::map<int, Rule> cache;
+    static std::mutex mu;
+    return cached_rule(cache, mu, q, build_tet_rule);
+}
+
+const Rule& tri_rule(int q) {
+    static std::map<int, Rule> cache;
+    static std::mutex mu;
+    return cached_rule(cache, mu, q, build_tri_rule);
 }
 
 std::vector<std::array<int, 3>> exponents(int p) {

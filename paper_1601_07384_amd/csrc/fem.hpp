@@ -38,8 +38,8 @@ struct Rule {
 // Conical-product (collapsed) rules with q points per direction, exact for
 // total degree 2q-1: reference tet {xi >= 0, sum <= 1} (weights sum 1/6) and
 // reference triangle {a, b >= 0, a + b <= 1} (weights sum 1/2).
-Rule tet_rule(int q);
-Rule tri_rule(int q);
+const Rule& tet_rule(int q);
+const Rule& tri_rule(int q);
 
 std::vector<std::array<int, 3>> exponents(int p);   // first index fastest
 

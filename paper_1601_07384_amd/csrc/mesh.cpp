@@ -115,7 +115,7 @@ static void dual_face_blocks(const NodalBasis& phi, int p, const std::array<V3, 
     for (int s = 0; s < 2; ++s) out.Q[s].assign(3 * N * N, 0.0);
     const Affine A[2] = {Affine(Vt), Affine(Vk)};
     const int q = p + 1;
-    const Rule tr = tet_rule(q);
+    const Rule& tr = tet_rule(q);
     std::vector<real> ps(N), ph(N), gr(3 * N), gx(3 * N);
     for (int s = 0; s < 2; ++s) {
         // sub-tetrahedron T_{i,j}: the face and the element's barycentre
@@ -143,7 +143,7 @@ static void dual_face_blocks(const NodalBasis& phi, int p, const std::array<V3, 
         }
     }
     // face part: - int_Gamma psi phi_i n_ij  (n_ij outward of element i)
-    const Rule fr = tri_rule(q);
+    const Rule& fr = tri_rule(q);
     const V3 e1 = sub(P[1], P[0]), e2 = sub(P[2], P[0]);
     const real area2 = norm(cross(e1, e2));
     for (size_t m = 0; m < fr.w.size(); ++m) {

@@ -69,7 +69,7 @@ void face_data(const NodalBasis& phi, int p, const std::array<V3, 4>& Vt, int f,
     const Affine A1(Vk ? *Vk : Vt);
     const Affine* A[2] = {&A0, &A1};
     const int q = p + 1;
-    const Rule tr = tet_rule(q);
+    const Rule& tr = tet_rule(q);
     std::vector<real> ps(N), ph(N), gr(3 * N), gx(3 * N);
     for (int s = 0; s < ns; ++s) {
         std::array<V3, 4> sv = {bc[s], P[0], P[1], P[2]};
@@ -97,7 +97,7 @@ void face_data(const NodalBasis& phi, int p, const std::array<V3, 4>& Vt, int f,
         }
     }
     o.Qvol = o.Q[0];
-    const Rule fr = tri_rule(q);
+    const Rule& fr = tri_rule(q);
     const V3 e1 = sub(P[1], P[0]), e2 = sub(P[2], P[0]);
     const real area2 = norm(cross(e1, e2));
     for (size_t m = 0; m < fr.w.size(); ++m) {
@@ -165,7 +165,7 @@ int build_picard_tables(stdg_mesh* m, const std::vector<int64_t>& rep) {
     const NodalBasis phi(p);
     // reference volume rule and tables
     {
-        const Rule vr = tet_rule(t.qv);
+        const Rule& vr = tet_rule(t.qv);
         t.PHv.assign((size_t)t.nqv * N, 0);
         t.dPHv.assign((size_t)t.nqv * N * 3, 0);
         t.wv.assign(t.nqv, 0);
@@ -178,7 +178,7 @@ int build_picard_tables(stdg_mesh* m, const std::vector<int64_t>& rep) {
             t.wv[q] = (double)vr.w[q];
         }
     }
-    const Rule fr = tri_rule(t.qs);
+    const Rule& fr = tri_rule(t.qs);
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
     for (int c = 0; c < C; ++c) {
@@ -187,7 +187,7 @@ int build_picard_tables(stdg_mesh* m, const std::vector<int64_t>& rep) {
         const Affine At(Vt);
         std::vector<real> Mi(NN, 0), tmp(NN), tmp3(3 * NN), SV0(NN, 0), SVk(NN);
         {   // element mass
-            const Rule tr = tet_rule(p + 1);
+            const Rule& tr = tet_rule(p + 1);
             std::vector<real> ph(N);
             const real jac = std::fabs(At.det);
             for (size_t q = 0; q < tr.w.size(); ++q) {
