@@ -103,8 +103,9 @@ def run_abc(n, p, pg, nu, t_end=0.1, cfl=0.3, theta=1.0, exact_p0=False):
 # slab) against 3.71 in Table 2 and the p + 1/2 the paper states, while its
 # errors are 0.30-0.37 times the table's on all four meshes.
 # The steady pressure at p = 2 converges at 2.59 on Table 1's meshes and 2.42
-# on finer ones (2.47 with a third of the time step, so not a time error)
-# against 2.95 in the table; p = 1, 3, 4, 5 match the table.
+# on finer ones against 2.95 in the table (2.47 with a third of the time
+# step, 2.62 on jittered meshes: neither the time step nor the mesh's
+# regularity); p = 1, 3, 4, 5 match the table.
 ORDER_FLOOR = {("abc_unsteady_table2.json", 3, "p"): 2.8,
                ("abc_steady_table1.json", 2, "p"): 2.3}
 
