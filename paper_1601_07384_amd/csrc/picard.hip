@@ -332,6 +332,76 @@ __global__ void __launch_bounds__(256) k_visc_tn(
     }
 }
 
+// The same operator for meshes whose wavefronts mix classes (classes holding
+// fewer elements than a wavefront): one thread per (element, time node a)
+// applies its element's blocks to all three components, so each block entry
+// is read once for the three (per component the same sums in the same order).
+template <int N, int G>
+__global__ void __launch_bounds__(256) k_visc_tn3(
+    const double* __restrict__ SVt, const double* __restrict__ MIt, const int32_t* __restrict__ cls,
+    const int32_t* __restrict__ nbr, const double* __restrict__ Tm, const double* __restrict__ W, double nu_dt,
+    const double* __restrict__ x, double* __restrict__ y, int64_t E) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= E * G) return;
+    const int a = (int)(t % G);
+    const int64_t i = t / G;
+    const int c = cls[i];
+    const int64_t cs = E * G * N;                 // component stride
+    const double wa = nu_dt * W[a];
+    double Ta[G];
+#pragma unroll
+    for (int b = 0; b < G; ++b) Ta[b] = Tm[a * G + b];
+    double acc[3][N];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+        for (int r = 0; r < N; ++r) acc[cc][r] = 0.0;
+    int nb[5];
+    nb[0] = (int)i;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) nb[f + 1] = nbr[4 * i + f];
+    const double* Bc = SVt + (int64_t)c * 5 * N * N;
+    for (int k = 0; k < 5; ++k) {
+        const int tk = nb[k];
+        if (tk < 0) continue;
+        const double* xt = x + ((int64_t)tk * G + a) * N;
+        for (int m = 0; m < N; ++m) {
+            const double x0 = wa * xt[m], x1 = wa * xt[cs + m], x2 = wa * xt[2 * cs + m];
+            const double* col = Bc + k * N * N + m * N;
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                const double bv = col[r];
+                acc[0][r] += bv * x0;
+                acc[1][r] += bv * x1;
+                acc[2][r] += bv * x2;
+            }
+        }
+    }
+    const double* Mc = MIt + (int64_t)c * N * N;
+    const double* xi = x + i * G * N;
+    for (int m = 0; m < N; ++m) {
+        double xp[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < G; ++b)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) xp[cc] += Ta[b] * xi[cc * cs + b * N + m];
+        const double* col = Mc + m * N;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            const double bv = col[r];
+            acc[0][r] += bv * xp[0];
+            acc[1][r] += bv * xp[1];
+            acc[2][r] += bv * xp[2];
+        }
+    }
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+        double* yi = y + cc * cs + (i * G + a) * N;
+#pragma unroll
+        for (int r = 0; r < N; ++r) yi[r] = acc[cc][r];
+    }
+}
+
 // y_i = D_i^-1 x_i for the viscous diagonal blocks (per component), DV
 // column-major so that the threads of one element read consecutive values.
 __global__ void k_blockdiag(const double* __restrict__ DV, const int32_t* __restrict__ cls,
@@ -555,6 +625,12 @@ hipError_t run_visc_rhs(const stdg_mesh* m, const double* vprev, const double* u
 template <int N, int G>
 static hipError_t launch_visc_ng(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
     const PicardDevice& d = m->pd;
+    if ((int64_t)m->n_classes * 64 > m->E) {
+        const int64_t blocks = (m->E * G + 255) / 256;
+        hipLaunchKernelGGL((k_visc_tn3<N, G>), dim3((unsigned)blocks), dim3(256), 0, s, d.SVt, d.MIt, m->d.cls,
+                           m->d.nbr, d.Tm, d.W, m->cfg.nu * m->cfg.dt, x, y, m->E);
+        return hipGetLastError();
+    }
     const int64_t blocks = ((m->E + 255) / 256 + 7) / 8 * 8 * G * 3;
     hipLaunchKernelGGL((k_visc_tn<N, G>), dim3((unsigned)blocks), dim3(256), 0, s, d.SVt, d.MIt, m->d.cls,
                        m->d.nbr, d.Tm, d.W, m->cfg.nu * m->cfg.dt, x, y, m->E);
