@@ -223,6 +223,34 @@ __global__ void __launch_bounds__(256) kf_blockdiag(const double* __restrict__ D
     store_row<NG>(y + t * NG, acc, 1.0);
 }
 
+// The same product for meshes whose wavefronts mix classes: one thread per
+// (element, row) forms that row for all three components, so each inverse
+// entry is read once for the three; neighbouring threads read neighbouring
+// rows of the column-major block (per output the same sum in the same order).
+template <int NG>
+__global__ void __launch_bounds__(256) kf_blockdiag3(const double* __restrict__ DV, const int32_t* __restrict__ cls,
+                                                     const double* __restrict__ x, double* __restrict__ y, int64_t E) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= E * NG) return;
+    const int64_t i = t / NG;
+    const int r = (int)(t - i * NG);
+    const double* D = DV + (int64_t)cls[i] * NG * NG + r;
+    const double* x0 = x + i * NG;
+    const int64_t cs = E * NG;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 8
+    for (int m = 0; m < NG; ++m) {
+        const double d = D[m * NG];
+        a0 += d * x0[m];
+        a1 += d * x0[cs + m];
+        a2 += d * x0[2 * cs + m];
+    }
+    double* yo = y + i * NG + r;
+    yo[0] = a0;
+    yo[cs] = a1;
+    yo[2 * cs] = a2;
+}
+
 inline unsigned nb(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 255) / 256); }
 
 template <int N>
@@ -267,7 +295,10 @@ struct Launch {
 
 template <int NG>
 hipError_t blockdiag_ng(const stdg_mesh* m, const double* x, double* y, hipStream_t s) {
-    hipLaunchKernelGGL(kf_blockdiag<NG>, dim3(nb(3 * m->E)), dim3(256), 0, s, m->pd.DV, m->d.cls, x, y, m->E);
+    if ((int64_t)m->n_classes * 64 > m->E)
+        hipLaunchKernelGGL(kf_blockdiag3<NG>, dim3(nb(m->E * NG)), dim3(256), 0, s, m->pd.DV, m->d.cls, x, y, m->E);
+    else
+        hipLaunchKernelGGL(kf_blockdiag<NG>, dim3(nb(3 * m->E)), dim3(256), 0, s, m->pd.DV, m->d.cls, x, y, m->E);
     return hipGetLastError();
 }
 
