@@ -193,7 +193,7 @@ def viscous_matrix(ops, nu):
         Minv = linalg.inv(F["Mbar"])
         for s in F["sides"]:
             for t in F["sides"]:
-                blk = -nu * np.einsum("dkl,lm,dmn->kn", F[("D", s)], Minv, F[("Q", t)])
+                blk = -nu * np.einsum("dkm,dmn->kn", np.einsum("dkl,lm->dkm", F[("D", s)], Minv), F[("Q", t)])
                 put(F[("elem", s)], F[("elem", t)], blk)
     n = mesh.E * Nst
     return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),

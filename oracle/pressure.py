@@ -65,7 +65,7 @@ def assemble_S(ops):
         Minv = linalg.inv(F["M"])
         for s in (0, 1):
             for t in (0, 1):
-                blk = -np.einsum("dkl,lm,dmn->kn", F[("D", s)], Minv, F[("Q", t)])
+                blk = -np.einsum("dkm,dmn->kn", np.einsum("dkl,lm->dkm", F[("D", s)], Minv), F[("Q", t)])
                 i, k = F[("elem", s)], F[("elem", t)]
                 r, c = np.meshgrid(np.arange(Nst) + i * Nst, np.arange(Nst) + k * Nst,
                                    indexing="ij")
