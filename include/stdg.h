@@ -212,6 +212,23 @@ int stdg_pressure_solve(const stdg_mesh* mesh, const double* b, double* x,
                         const stdg_solve_opts* opts, stdg_solve_report* report,
                         void* stream);
 
+/* The solve of stdg_pressure_solve without any device allocation, for
+ * callers that cannot allocate (tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and report; supported only with
+ * precision STDG_FP64 and method STDG_CG (p_gamma = 0) or STDG_CG_TIME (any
+ * p_gamma; STDG_AUTO resolves to CG at p_gamma = 0), other options give
+ * STDG_ERR_ARG.  Every work buffer (four vectors of E*N_st doubles, the
+ * reduction partials and the device scalars) lives in one fixed device array
+ * of 35.6 MB that each GPU the library runs on holds until the process ends,
+ * so E*N_st may be at most 1,048,576 (STDG_ERR_ARG otherwise).  Every call on
+ * a GPU shares that GPU's array, which keeps the last call's contents: calls
+ * that overlap on one GPU (two host threads, or two streams) race.  It calls
+ * no hipMalloc/hipFree; the host waits on `stream` as stdg_pressure_solve
+ * does. */
+int stdg_pressure_solve_noalloc(const stdg_mesh* mesh, const double* b, double* x,
+                                const stdg_solve_opts* opts, stdg_solve_report* report,
+                                void* stream);
+
 /* ---------------------------------------------------------------------------
  * Picard pressure-correction time step (Sec. 2.6, steps 0-6).
  *

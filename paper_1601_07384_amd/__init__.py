@@ -157,6 +157,17 @@ class Mesh:
         _lib.check(code, allow=(STDG_OK, STDG_NOT_CONVERGED))
         return rep
 
+    def solve_noalloc(self, b, x, opts=None, stream=None, **kw):
+        """The same solve (FP64, STDG_CG or STDG_CG_TIME) on the library's
+        fixed device scratch array: no device allocation.  Returns the report."""
+        self._check_vec(b, "float64"); self._check_vec(x, "float64")
+        o = opts if opts is not None else solve_opts(**kw)
+        rep = SolveReport()
+        code = self._lib.stdg_pressure_solve_noalloc(self._h, _ptr(b), _ptr(x), ctypes.byref(o),
+                                                     ctypes.byref(rep), _stream_ptr(stream))
+        _lib.check(code, allow=(STDG_OK, STDG_NOT_CONVERGED))
+        return rep
+
     # -------------------------------------------------------------- Picard
     def picard_step(self, vhat, vbar, p, g_nodal=None, opts=None, stream=None, **kw):
         """One time step (in place on vhat [3,F,G,N], vbar [3,E,G,N], p [E,G,N])."""

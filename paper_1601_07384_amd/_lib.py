@@ -121,6 +121,8 @@ SIGNATURES = [
     ("stdg_solve_opts_default", None, [ctypes.POINTER(SolveOpts)]),
     ("stdg_pressure_solve", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(SolveOpts),
                                             ctypes.POINTER(SolveReport), _P]),
+    ("stdg_pressure_solve_noalloc", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(SolveOpts),
+                                                    ctypes.POINTER(SolveReport), _P]),
     ("stdg_step_opts_default", None, [ctypes.POINTER(StepOpts)]),
     ("stdg_picard_step", ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.POINTER(StepOpts),
                                          ctypes.POINTER(StepReport), _P]),

@@ -21,6 +21,8 @@
 // the outer residual b~ - S x is recomputed in FP64 each refinement step.
 #include <chrono>
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include <type_traits>
@@ -939,13 +941,12 @@ extern "C" void stdg_solve_opts_default(stdg_solve_opts* o) {
     o->precond = STDG_PRECOND_BLOCK_JACOBI;
 }
 
-extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double* x,
-                                   const stdg_solve_opts* opts, stdg_solve_report* rep, void* stream) {
-    auto t0 = std::chrono::steady_clock::now();
-    if (!cm || !b || !x || !opts) { set_error("null argument"); return STDG_ERR_ARG; }
-    stdg_mesh* m = const_cast<stdg_mesh*>(cm);
-    if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
-    stdg_solve_opts o = *opts;
+namespace stdg {
+namespace {
+
+// Checks the options of a pressure solve and resolves STDG_AUTO; mres is set
+// to the number of basis vectors the method keeps (0 for the CG methods).
+int check_solve_opts(const stdg_mesh* m, stdg_solve_opts& o, int& mres) {
     if (o.method == STDG_AUTO) o.method = (m->G == 1) ? STDG_CG : STDG_GMRES;
     if (o.method != STDG_CG && o.method != STDG_GMRES && o.method != STDG_CG_TIME && o.method != STDG_BICGSTAB) {
         set_error("unknown method");
@@ -959,11 +960,20 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
     if (!(o.rtol > 0.0) || o.max_iter < 1 || o.check_every < 1) { set_error("bad tolerance/iteration options"); return STDG_ERR_ARG; }
     if (o.precond != STDG_PRECOND_NONE && o.precond != STDG_PRECOND_BLOCK_JACOBI) { set_error("bad preconditioner"); return STDG_ERR_ARG; }
     if (o.precision != STDG_FP64 && o.precision != STDG_FP32) { set_error("bad precision"); return STDG_ERR_ARG; }
+    if (o.precision == STDG_FP32 && (!(o.inner_rtol > 0.0) || o.max_outer < 1)) {
+        set_error("bad refinement options");
+        return STDG_ERR_ARG;
+    }
+    mres = (o.method == STDG_GMRES) ? o.restart : (o.method == STDG_BICGSTAB ? 2 : 0);
+    return STDG_OK;
+}
+
+// The anchored solve itself, on the work buffers of w (vectors r, p, q, z of
+// w.n doubles, the GMRES/BiCGStab basis V, the FP32 vectors when o asks for
+// refinement, reduction partials, device scalars and a host mirror).
+int solve_with(stdg_mesh* m, const double* b, double* x, const stdg_solve_opts& o, int mres,
+               stdg_solve_report* rep, void* stream, Workspace& w, std::chrono::steady_clock::time_point t0) {
     const bool ir = o.precision == STDG_FP32;
-    if (ir && (!(o.inner_rtol > 0.0) || o.max_outer < 1)) { set_error("bad refinement options"); return STDG_ERR_ARG; }
-    const int mres = (o.method == STDG_GMRES) ? o.restart : (o.method == STDG_BICGSTAB ? 2 : 0);
-    if (int e = ensure_workspace(m, mres, ir)) return e;
-    Workspace& w = m->ws;
     Ctx c;
     c.m = m;
     c.s = (hipStream_t)stream;
@@ -1079,6 +1089,100 @@ extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double*
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return status;
+}
+
+}  // namespace
+}  // namespace stdg
+
+extern "C" int stdg_pressure_solve(const stdg_mesh* cm, const double* b, double* x,
+                                   const stdg_solve_opts* opts, stdg_solve_report* rep, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!cm || !b || !x || !opts) { set_error("null argument"); return STDG_ERR_ARG; }
+    stdg_mesh* m = const_cast<stdg_mesh*>(cm);
+    if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
+    stdg_solve_opts o = *opts;
+    int mres = 0;
+    if (int e = check_solve_opts(m, o, mres)) return e;
+    if (int e = ensure_workspace(m, mres, o.precision == STDG_FP32)) return e;
+    return solve_with(m, b, x, o, mres, rep, stream, m->ws, t0);
+}
+
+// ------------------------------------------------------------------ no-allocation solve
+// The FP64 CG solves (STDG_CG, STDG_CG_TIME) with every work buffer in one
+// file-scope device array: four vectors of at most NOALLOC_MAX_DOF doubles,
+// the reduction partials and the device scalars (35.6 MB per GPU, held until
+// the process ends).  Host code never uses the array's name as an address:
+// each device's copy is looked up once with hipGetSymbolAddress.
+namespace stdg {
+namespace {
+
+constexpr int64_t NOALLOC_MAX_DOF = int64_t(1) << 20;
+constexpr int64_t SCR_PARTIAL = (int64_t)NBLK * 208;
+constexpr int64_t SCR_SCAL = S_COUNT + 4 * 256 + 208 * 208;
+constexpr int64_t SCR_DOUBLES = 4 * NOALLOC_MAX_DOF + SCR_PARTIAL + SCR_SCAL;
+
+static __device__ __align__(256) double scratch[SCR_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_dev[MAX_DEVICES] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device).
+int scratch_address(double** out) {
+    int dev = 0;
+    STDG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) { set_error("device index out of range"); return STDG_ERR_DEVICE; }
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* ptr = nullptr;
+        STDG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) { set_error("no device address for the scratch array"); return STDG_ERR_DEVICE; }
+        scratch_dev[dev] = static_cast<double*>(ptr);
+    }
+    *out = scratch_dev[dev];
+    return STDG_OK;
+}
+
+}  // namespace
+}  // namespace stdg
+
+extern "C" int stdg_pressure_solve_noalloc(const stdg_mesh* cm, const double* b, double* x,
+                                           const stdg_solve_opts* opts, stdg_solve_report* rep, void* stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!cm || !b || !x || !opts) { set_error("null argument"); return STDG_ERR_ARG; }
+    stdg_mesh* m = const_cast<stdg_mesh*>(cm);
+    if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
+    stdg_solve_opts o = *opts;
+    int mres = 0;
+    if (int e = check_solve_opts(m, o, mres)) return e;
+    if (o.precision != STDG_FP64 || (o.method != STDG_CG && o.method != STDG_CG_TIME)) {
+        set_error("the no-allocation solve supports FP64 precision with STDG_CG or STDG_CG_TIME only");
+        return STDG_ERR_ARG;
+    }
+    const int64_t n = m->E * (int64_t)m->Nst;
+    if (n > NOALLOC_MAX_DOF) {
+        set_error("the no-allocation solve holds at most " + std::to_string(NOALLOC_MAX_DOF) +
+                  " pressure unknowns; this mesh has " + std::to_string(n));
+        return STDG_ERR_ARG;
+    }
+    double* base = nullptr;
+    if (int e = scratch_address(&base)) return e;
+    Workspace w;
+    w.n = (size_t)n;
+    w.r = base;
+    w.p = base + NOALLOC_MAX_DOF;
+    w.q = base + 2 * NOALLOC_MAX_DOF;
+    w.z = base + 3 * NOALLOC_MAX_DOF;
+    w.partial = base + 4 * NOALLOC_MAX_DOF;
+    w.scal = w.partial + SCR_PARTIAL;
+    double host_mirror[8] = {0.0};
+    w.hscal = host_mirror;
+    // the previous call's scalars are cleared by a kernel (no memset node)
+    hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(SCR_SCAL)), dim3(256), 0, (hipStream_t)stream, w.scal, 0.0,
+                       SCR_SCAL);
+    CK(hipGetLastError());
+    return solve_with(m, b, x, o, mres, rep, stream, w, t0);
 }
 
 // y = (B (x) I) x in FP32 with the CG operator kernel.
