@@ -102,6 +102,55 @@ def test_apply_c4_full_size_sampled_rows():
     assert _sampled_rows(16, 4, 4, False, 1e-2, 6, 6) <= 1e-12
 
 
+def test_apply_c3_full_size_sampled_rows():
+    """48^3 x 6 = 663,552 tets, p=3, p_gamma=0, periodic: sampled rows."""
+    print("case C3 sampled", flush=True)
+    assert _sampled_rows(48, 3, 0, True, 1e-3, 24, 7) <= 1e-12
+
+
+def test_apply_c5_full_size_sampled_rows():
+    """32^3 x 6 = 196,608 tets, p=2, p_gamma=1, periodic: sampled rows."""
+    print("case C5 sampled", flush=True)
+    assert _sampled_rows(32, 2, 1, True, 1e-3, 24, 8) <= 1e-12
+
+
+def _time_factor_inverse(pg):
+    """C^-1 for C = W T^-1 W from the hand-derived time matrices (p_gamma <= 1)."""
+    if pg == 0:
+        return np.eye(1)
+    Tc = np.array([[1.0, (np.sqrt(3.0) - 1) / 2], [-(np.sqrt(3.0) + 1) / 2, 1.0]])
+    W = 0.5 * np.eye(2)
+    return np.linalg.inv(W @ np.linalg.inv(Tc) @ W)
+
+
+@pytest.mark.parametrize("n,p,pg", [(8, 3, 1), (48, 3, 0), (32, 2, 1), (24, 3, 1)])
+def test_spatial_apply_f32_sampled_rows(n, p, pg):
+    """The FP32 spatial operator (B (x) I) of the time-decoupled inner solve on
+    periodic cubes whose 64-element runs share a class, so the cycle-staged
+    kernel runs with its halo rows (8^3: 8 chunks; the 663,552-, 196,608- and
+    82,944-element cubes at full size): sampled rows against the oracle's
+    S (I (x) C^-1) x, 1e-5 relative."""
+    print(f"spatial f32 sampled n={n} p={p} pg={pg}", flush=True)
+    dt = 1e-3
+    X, T = kuhn_mesh(n)
+    m = P.Mesh(X, T, p, pg, dt=dt, periodic=True)
+    ops = SpaceTimeOperators(OracleMesh(X, T, periodic=True), p, pg, dt)
+    rng = np.random.default_rng(40 + n)
+    x = rng.standard_normal((m.E, m.G, m.N)).astype(np.float32).astype(np.float64)
+    xs = np.einsum("ab,ebn->ean", _time_factor_inverse(pg), x).reshape(m.E, m.Nst)
+    perm = m.permutation()
+    xf = gpu(x.reshape(m.E, m.Nst)[perm].ravel(), torch.float32)
+    yf = torch.empty_like(xf)
+    m.apply_spatial_f32(xf, yf)
+    torch.cuda.synchronize()
+    yg = to_input(yf.cpu().numpy().astype(np.float64).reshape(m.E, m.Nst), perm)
+    rows = np.concatenate([rng.choice(m.E, size=24, replace=False), [0, m.E - 1]])
+    yo = apply_S(ops, xs, elements=rows)
+    err = np.abs(yg[rows] - yo[rows]).max() / np.abs(yo[rows]).max()
+    print(f"  max relative difference {err:.2e}", flush=True)
+    assert err <= 1e-5
+
+
 def test_apply_c3_full_size_properties():
     """48^3 x 6 = 663,552 tets, p=3, p_gamma=0, periodic: S 1 = 0, symmetry
     <Sx, z> = <x, Sz>, and the Green closed form S q = -dt^2 int phi Lap q for
@@ -172,6 +221,8 @@ SOLVE = [  # n, p, pg, periodic, jitter, method, precision
     (3, 2, 1, True, 0.0, P.STDG_BICGSTAB, P.STDG_FP32),
     (3, 2, 1, True, 0.1, P.STDG_CG_TIME, P.STDG_FP32),   # fused FP32 PCG, every tile mixing classes
     (3, 3, 0, True, 0.1, P.STDG_CG, P.STDG_FP32),
+    (8, 2, 0, True, 0.0, P.STDG_CG, P.STDG_FP32),     # cycle-staged FP32 PCG, 8 chunks with halos
+    (8, 3, 0, True, 0.0, P.STDG_CG, P.STDG_FP32),     # the same at the headline degree (N = 20)
 ]
 
 
