@@ -229,7 +229,7 @@ def main():
     fp64_us = median_launch_us(lambda: m.apply(x64, y64))
     op32 = None
     try:
-        xf = torch.randn(n, dtype=torch.float32, device=dev)
+        xf = torch.randn(m.inner_len, dtype=torch.float32, device=dev)
         yf = torch.empty_like(xf)
         op32 = median_launch_us(lambda: m.apply_spatial_f32(xf, yf))
         del xf, yf

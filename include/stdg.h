@@ -94,7 +94,21 @@ typedef struct {
     int32_t N, G, Nst;          /* N spatial functions, G time nodes, N*G     */
     int32_t n_classes;          /* distinct operator block sets stored        */
     int64_t anchor_internal;    /* internal index of the anchor element       */
+    int32_t inner_layout;       /* STDG_LAYOUT_ELEMENT or STDG_LAYOUT_RUN:    */
+                                /* layout of the FP32 inner-solve vectors     */
+    int64_t inner_len;          /* floats in one such vector                  */
 } stdg_mesh_info;
+
+/* Layouts of FP32 vectors of the inner (refinement) solve.
+ * STDG_LAYOUT_ELEMENT: [E][G][N] like every FP64 vector.
+ * STDG_LAYOUT_RUN (meshes whose consecutive 64-element runs each hold one
+ * geometry class, e.g. the class-chunked Kuhn cubes): value k of element
+ * e = 64 R + l at time node a is entry (((R G + a) (N / w) + k / w) 64 + l) w
+ * + k % w with w = 4 if 4 divides N, else 2 if 2 does, else 1; the length is
+ * ceil(E / 64) 64 G N and the entries of the missing elements of a ragged
+ * last run are zero. */
+#define STDG_LAYOUT_ELEMENT 0
+#define STDG_LAYOUT_RUN 1
 
 /* Build the primary mesh, its face-based dual mesh (Sec. 2.2.1) and every
  * precomputed operator block (the paper precomputes and stores all coefficient
@@ -189,10 +203,21 @@ typedef struct {
 
 /* y = (B (x) I) x in FP32: the spatial Schur operator B = dt^2 S^sp of
  * eq. CS_19 (F3 factorisation S = B (x) C) on every time node, i.e. the
- * operator of the time-decoupled solve (STDG_CG_TIME).  x, y: device
- * [E][G][N] floats, 16-byte aligned.  Runs the FP32 MFMA kernel of the fused
- * CG iteration (p = 1, 2, 3).  Asynchronous; uses the mesh's workspace. */
+ * operator of the time-decoupled solve (STDG_CG_TIME) and, times the scalar
+ * C, of the p_gamma = 0 solve.  x, y: device floats in the mesh's inner
+ * layout (stdg_mesh_info.inner_layout, inner_len entries), 16-byte aligned,
+ * not overlapping.  Runs the FP32 MFMA kernel of the fused CG iteration
+ * (p = 1, 2, 3; STDG_ERR_ARG otherwise).  Asynchronous. */
 int stdg_pressure_apply_spatial_f32(const stdg_mesh* mesh, const float* x, float* y, void* stream);
+
+/* Moves between FP64 vectors ([E][G][N] doubles, device) and FP32 vectors in
+ * the mesh's inner layout (inner_len floats, device): y = (float)(scale x),
+ * padding entries set to zero; and x = scale y.  These are the conversions
+ * the refinement solve applies around its FP32 inner solves (the residual
+ * scaled to unit norm, the correction scaled back).  Asynchronous on
+ * `stream`.  Errors: STDG_ERR_ARG (null pointer, host-only mesh). */
+int stdg_inner_from_f64(const stdg_mesh* mesh, const double* x, double scale, float* y, void* stream);
+int stdg_inner_to_f64(const stdg_mesh* mesh, const float* y, double scale, double* x, void* stream);
 
 /* Fill opts with defaults: AUTO, restart 50, rtol 1e-10, max_iter 20000,
  * FP64, inner_rtol 1e-4, max_outer 30, check_every 8. */

@@ -17,13 +17,15 @@ from ._lib import (Config, MeshInfo, SolveOpts, SolveReport, StepOpts, StepRepor
                    STDG_AUTO, STDG_CG, STDG_GMRES, STDG_CG_TIME, STDG_GUESS_ZERO,
                    STDG_GUESS_PREVIOUS, STDG_KRYLOV_ZERO, STDG_KRYLOV_PREVIOUS,
                    STDG_KRYLOV_EXTRAPOLATE, STDG_KRYLOV_LEARNED, STDG_LOSS_MSE, STDG_LOSS_RESIDUAL,
-                   STDG_PRECOND_NONE, STDG_PRECOND_BLOCK_JACOBI, STDG_BICGSTAB)
+                   STDG_PRECOND_NONE, STDG_PRECOND_BLOCK_JACOBI, STDG_BICGSTAB,
+                   STDG_LAYOUT_ELEMENT, STDG_LAYOUT_RUN)
 
 __all__ = ["Mesh", "Model", "StdgError", "STDG_FP64", "STDG_FP32", "STDG_AUTO",
            "STDG_CG", "STDG_GMRES", "STDG_CG_TIME", "STDG_GUESS_ZERO", "STDG_GUESS_PREVIOUS",
            "STDG_KRYLOV_ZERO", "STDG_KRYLOV_PREVIOUS", "STDG_KRYLOV_EXTRAPOLATE",
            "STDG_KRYLOV_LEARNED", "STDG_LOSS_MSE", "STDG_LOSS_RESIDUAL", "STDG_PRECOND_NONE",
-           "STDG_PRECOND_BLOCK_JACOBI", "STDG_BICGSTAB", "solve_opts", "step_opts"]
+           "STDG_PRECOND_BLOCK_JACOBI", "STDG_BICGSTAB", "STDG_LAYOUT_ELEMENT", "STDG_LAYOUT_RUN",
+           "solve_opts", "step_opts"]
 
 
 def _stream_ptr(stream):
@@ -97,6 +99,7 @@ class Mesh:
         self.n_face, self.n_interior_face = info.n_face, info.n_interior_face
         self.n_classes = info.n_classes
         self.anchor_internal = info.anchor_internal
+        self.inner_layout, self.inner_len = info.inner_layout, info.inner_len
         self.p, self.p_gamma, self.dt, self.nu = p, p_gamma, dt, nu
 
     def __del__(self):
@@ -142,10 +145,23 @@ class Mesh:
                                                      _stream_ptr(stream)))
 
     def apply_spatial_f32(self, x, y, stream=None):
-        """y = (B (x) I) x: the spatial operator on every time node, FP32."""
-        self._check_vec(x, "float32"); self._check_vec(y, "float32")
+        """y = (B (x) I) x: the spatial operator on every time node, FP32,
+        vectors in the inner layout (inner_len entries)."""
+        self._check_vec(x, "float32", self.inner_len); self._check_vec(y, "float32", self.inner_len)
         _lib.check(self._lib.stdg_pressure_apply_spatial_f32(self._h, _ptr(x), _ptr(y),
                                                              _stream_ptr(stream)))
+
+    def inner_from_f64(self, x, y, scale=1.0, stream=None):
+        """y (FP32, inner layout) = scale x (FP64, [E][G][N])."""
+        self._check_vec(x, "float64"); self._check_vec(y, "float32", self.inner_len)
+        _lib.check(self._lib.stdg_inner_from_f64(self._h, _ptr(x), float(scale), _ptr(y),
+                                                 _stream_ptr(stream)))
+
+    def inner_to_f64(self, y, x, scale=1.0, stream=None):
+        """x (FP64, [E][G][N]) = scale y (FP32, inner layout)."""
+        self._check_vec(y, "float32", self.inner_len); self._check_vec(x, "float64")
+        _lib.check(self._lib.stdg_inner_to_f64(self._h, _ptr(y), float(scale), _ptr(x),
+                                               _stream_ptr(stream)))
 
     def solve(self, b, x, opts=None, stream=None, **kw):
         """Anchored pressure solve; x holds the guess on entry.  Returns the report."""
@@ -214,11 +230,12 @@ class Mesh:
         if t.numel() != n:
             raise ValueError(f"expected {n} entries, got {t.numel()}")
 
-    def _check_vec(self, t, dtype):
+    def _check_vec(self, t, dtype, n=None):
         if not t.is_cuda or str(t.dtype) != "torch." + dtype or not t.is_contiguous():
             raise ValueError(f"expected a contiguous CUDA {dtype} tensor")
-        if t.numel() != self.E * self.Nst:
-            raise ValueError(f"expected {self.E * self.Nst} entries, got {t.numel()}")
+        n = self.E * self.Nst if n is None else n
+        if t.numel() != n:
+            raise ValueError(f"expected {n} entries, got {t.numel()}")
 
 
 class Model:

@@ -17,6 +17,8 @@ STDG_ERR_MESH = -2
 STDG_ERR_NUMERIC = -3
 STDG_ERR_DEVICE = -4
 STDG_ERR_NOMEM = -5
+STDG_LAYOUT_ELEMENT = 0
+STDG_LAYOUT_RUN = 1
 STDG_FP64 = 0
 STDG_FP32 = 1
 STDG_AUTO = 0
@@ -38,7 +40,8 @@ class MeshInfo(ctypes.Structure):
     _fields_ = [("n_tet", ctypes.c_int64), ("n_face", ctypes.c_int64),
                 ("n_interior_face", ctypes.c_int64),
                 ("N", ctypes.c_int32), ("G", ctypes.c_int32), ("Nst", ctypes.c_int32),
-                ("n_classes", ctypes.c_int32), ("anchor_internal", ctypes.c_int64)]
+                ("n_classes", ctypes.c_int32), ("anchor_internal", ctypes.c_int64),
+                ("inner_layout", ctypes.c_int32), ("inner_len", ctypes.c_int64)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -118,6 +121,8 @@ SIGNATURES = [
     ("stdg_pressure_apply", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     ("stdg_pressure_apply_f32", ctypes.c_int, [_P, _P, _P, _P]),
     ("stdg_pressure_apply_spatial_f32", ctypes.c_int, [_P, _P, _P, _P]),
+    ("stdg_inner_from_f64", ctypes.c_int, [_P, _P, ctypes.c_double, _P, _P]),
+    ("stdg_inner_to_f64", ctypes.c_int, [_P, _P, ctypes.c_double, _P, _P]),
     ("stdg_solve_opts_default", None, [ctypes.POINTER(SolveOpts)]),
     ("stdg_pressure_solve", ctypes.c_int, [_P, _P, _P, ctypes.POINTER(SolveOpts),
                                             ctypes.POINTER(SolveReport), _P]),

@@ -65,8 +65,8 @@ int upload_tables(stdg_mesh* m) {
 void free_tables(stdg_mesh* m) {
     for (void* p : {(void*)m->d.blocks, (void*)m->d.blocks32, (void*)m->d.aop32, (void*)m->d.cls, (void*)m->d.nbr,
                     (void*)m->d.C, (void*)m->d.C32, (void*)m->d.Cinv, (void*)m->d.Cinv32,
-                    (void*)m->d.Cid, (void*)m->d.Cid32, (void*)m->d.cyc_slot, (void*)m->d.cyc_halo,
-                    (void*)m->d.cyc_aop})
+                    (void*)m->d.Cid, (void*)m->d.Cid32, (void*)m->d.chunk_slot, (void*)m->d.chunk_halo,
+                    (void*)m->d.lane_ops})
         if (p) (void)hipFree(p);
     m->d = DeviceTables();
 }
@@ -167,6 +167,9 @@ extern "C" int stdg_mesh_info_get(const stdg_mesh* m, stdg_mesh_info* info) {
     info->Nst = m->Nst;
     info->n_classes = m->n_classes;
     info->anchor_internal = m->anchor;
+    const bool run = lane_supported(m);
+    info->inner_layout = run ? STDG_LAYOUT_RUN : STDG_LAYOUT_ELEMENT;
+    info->inner_len = run ? lane_len(m) : m->E * m->G * m->N;
     return STDG_OK;
 }
 

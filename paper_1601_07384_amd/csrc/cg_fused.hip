@@ -501,325 +501,11 @@ __global__ void __launch_bounds__(256) k_cg_prec(const float* __restrict__ A, co
     if (REM > 0) bstore<1>(ryo, offr, &o[W]);
 }
 
-// ------------------------------------------------------- cycle-staged iteration
-// The same iteration (and, with ITER = false, the same operator) with the
-// neighbour rows staged in LDS.  One workgroup per (chunk of CYC consecutive
-// elements, time node).  The element order puts the six Kuhn classes of 64
-// hexahedra in six consecutive 64-element runs, so a chunk holds whole
-// hexahedra and most face neighbours of its elements (82 % on the structured
-// cubes) lie in the same chunk.
-//   Phase 1: wavefront w takes the 64-element run w (four 16-element tiles,
-//   lane slices as in k_cg_op), loads its own rows of z, w, p and x (a
-//   contiguous range per tile: coalesced), forms z_i = z - alpha w,
-//   p_i = z_i + beta p and x += alpha p, stores x and writes p_i to the
-//   element's LDS row; the chunk's halo rows (neighbours outside the chunk,
-//   listed per chunk on the host) are gathered once, updated the same way
-//   and written to LDS rows CYC + h.
-//   Phase 2: the B operands of the four neighbour blocks are read from LDS
-//   through the per-element slot table; products, stores and the partial
-//   dot products are those of k_cg_op.  A wavefront keeps the operands of
-//   the class it used last, so a class-uniform run loads them once.
-constexpr int CYC = 384;
-constexpr int CYC_W = CYC / 64;     // wavefronts per workgroup
-constexpr int CYC_T = 4;            // 16-element tiles per wavefront
-constexpr int CYC_HT = 3;           // halo tiles per wavefront at most (halo rows per chunk <= 288)
-
-template <int W> __device__ inline void lds_put(float* row, int kk, const float* v) {
-    if constexpr (W == 4) {
-        *reinterpret_cast<f4*>(row + 4 * kk) = f4{v[0], v[1], v[2], v[3]};
-    } else if constexpr (W == 2) {
-        *reinterpret_cast<f2*>(row + 2 * kk) = f2{v[0], v[1]};
-    } else {
-        row[kk] = v[0];
-    }
-}
-
-template <int W> __device__ inline void lds_get(const float* row, int kk, float* v) {
-    if constexpr (W == 4) {
-        const f4 t = *reinterpret_cast<const f4*>(row + 4 * kk);
-        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-    } else if constexpr (W == 2) {
-        const f2 t = *reinterpret_cast<const f2*>(row + 2 * kk);
-        v[0] = t.x; v[1] = t.y;
-    } else {
-        v[0] = row[kk];
-    }
-}
-
-template <int N, bool ITER>
-__global__ void __launch_bounds__(64 * CYC_W) k_cg_cyc(
-    const float* __restrict__ A, const int32_t* __restrict__ cls, const int16_t* __restrict__ slot,
-    const int32_t* __restrict__ halo, int hmax, int64_t n_chunks, float* x, const float* r_in, const float* p_in,
-    const float* q_in, float* r_out, float* p_out, float* q_out, const double* __restrict__ ab, float cscale,
-    int precond, int32_t E, int32_t G, uint32_t vbytes, double* __restrict__ part_out) {
-    typedef SliceShape<N> S;
-    constexpr int W = S::W, REM = S::REM, KS = S::KS, MT = S::MT, NB = S::NB;
-    extern __shared__ float rowsL[];                 // [CYC + hmax][N] rows of p_i (x for ITER = false)
-    __shared__ double sh[CYC_W * NPART];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int col = lane & 15, kk = lane >> 4;
-    // consecutive workgroups go round-robin to the 8 XCDs: XCD x takes the
-    // contiguous range of (chunk, time node) pairs x * per ..
-    const uint32_t lblock = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
-    const int64_t chunk = (int64_t)(lblock / (uint32_t)G);
-    const int a = (int)(lblock - (uint32_t)chunk * (uint32_t)G);
-    if (chunk >= n_chunks) {                         // padding workgroup
-        if (ITER && threadIdx.x < NPART) part_out[PSTRIDE * blockIdx.x + threadIdx.x] = 0.0;
-        return;
-    }
-    float alpha = 0.0f, beta = 0.0f;
-    if (ITER) {
-        alpha = (float)ab[0];
-        beta = (float)ab[1];
-    }
-    auto row_off = [&](int32_t row, uint32_t& off, uint32_t& offr) {
-        const uint32_t base = ((uint32_t)row * (uint32_t)G + (uint32_t)a) * (uint32_t)(4 * N);
-        off = row >= 0 ? base + 4u * (uint32_t)(W * kk) : OOB;
-        offr = (REM > 0 && row >= 0 && kk < REM) ? base + 4u * (uint32_t)(4 * W + kk) : OOB;
-    };
-    auto put_row = [&](int r, const float* v) {
-        float* row = rowsL + r * N;
-        lds_put<W>(row, kk, v);
-        if (REM > 0 && kk < REM) row[4 * W + kk] = v[W];
-    };
-    const Rsrc rr_in = make_rsrc(r_in, vbytes), rp_in = make_rsrc(p_in, vbytes), rq_in = make_rsrc(q_in, vbytes);
-    const Rsrc rx = make_rsrc(x, vbytes);
-    const Rsrc rs = make_rsrc(slot, 8u * (uint32_t)E);
-    const int32_t e0 = (int32_t)(chunk * CYC) + 64 * wave;
-    // the run's class (one per 64-element run, checked on the host); its
-    // operands are laid out per block ([class][6 blocks][NBP / 4][lane][4]:
-    // the five operator blocks, then the inverse of the own block) so that
-    // phase 2 holds one block at a time
-    constexpr int NBP = (NB + 3) / 4 * 4;
-    const int cw = e0 < E ? __builtin_amdgcn_readfirstlane(cls[e0]) : 0;
-    const f4* Ab = (const f4*)A + (size_t)cw * 6 * (NBP / 4) * 64;
-    float ablk[2][NBP];
-    ops_load<NBP>(Ab, lane, 0, ablk[0]);
-    // ---- phase 1.  Index loads first (slot table of the four tiles, halo
-    // element ids of the wavefront's halo tiles), then the rows in rounds
-    // that each keep every load of the round in flight: with ITER one round
-    // per two own tiles (own tiles 2r, 2r + 1 and halo tiles of round r),
-    // without it a single round.
-    typedef short s4 __attribute__((ext_vector_type(4)));
-    int32_t el[CYC_T];
-    bool vc[CYC_T];
-    s4 sl[CYC_T];
-    int32_t hg[CYC_HT];
-    const Rsrc rh = make_rsrc(halo, 4u * (uint32_t)(n_chunks * hmax));
-    const int nht = hmax / 16;
-#pragma unroll
-    for (int j = 0; j < CYC_T; ++j) {
-        el[j] = e0 + 16 * j + col;
-        vc[j] = el[j] < E;
-        sl[j] = __builtin_bit_cast(s4, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(vc[j] ? 8u * el[j] : OOB), 0, 0));
-    }
-#pragma unroll
-    for (int t = 0; t < CYC_HT; ++t) {
-        const int ht = wave + CYC_W * t;
-        const uint32_t ho = ht < nht ? 4u * (uint32_t)(chunk * hmax + 16 * ht + col) : OOB;
-        // an absent halo tile reads 0 here and is skipped below
-        hg[t] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rh, (int)ho, 0, 0);
-    }
-    float zn[CYC_T][KS];
-    constexpr int ROUNDS = ITER ? 2 : 1;
-    constexpr int OWN_R = CYC_T / ROUNDS;
-    constexpr int HAL_R = (CYC_HT + ROUNDS - 1) / ROUNDS;
-#pragma unroll
-    for (int rd = 0; rd < ROUNDS; ++rd) {
-        __builtin_amdgcn_sched_barrier(0);       // one round's loads live at a time
-        uint32_t off[OWN_R], offr[OWN_R];
-        float zv[OWN_R][KS], wv0[OWN_R][KS], pv0[OWN_R][KS], xv[OWN_R][KS];
-        uint32_t hof[HAL_R], hofr[HAL_R];
-        float hz[HAL_R][KS], hw[HAL_R][KS], hp[HAL_R][KS];
-#pragma unroll
-        for (int jj = 0; jj < OWN_R; ++jj) {
-            const int j = rd * OWN_R + jj;
-            row_off(vc[j] ? el[j] : -1, off[jj], offr[jj]);
-            bload<W>(rr_in, off[jj], zv[jj]);
-            if (REM > 0) bload<1>(rr_in, offr[jj], &zv[jj][W]);
-            if (ITER) {
-                bload<W>(rq_in, off[jj], wv0[jj]);
-                bload<W>(rp_in, off[jj], pv0[jj]);
-                bload<W>(rx, off[jj], xv[jj]);
-                if (REM > 0) {
-                    bload<1>(rq_in, offr[jj], &wv0[jj][W]);
-                    bload<1>(rp_in, offr[jj], &pv0[jj][W]);
-                    bload<1>(rx, offr[jj], &xv[jj][W]);
-                }
-            }
-        }
-#pragma unroll
-        for (int tt = 0; tt < HAL_R; ++tt) {
-            const int t = rd * HAL_R + tt;
-            const bool live = t < CYC_HT && wave + CYC_W * t < nht;
-            row_off(live ? hg[t < CYC_HT ? t : 0] : -1, hof[tt], hofr[tt]);
-            bload<W>(rr_in, hof[tt], hz[tt]);
-            if (REM > 0) bload<1>(rr_in, hofr[tt], &hz[tt][W]);
-            if (ITER) {
-                bload<W>(rq_in, hof[tt], hw[tt]);
-                bload<W>(rp_in, hof[tt], hp[tt]);
-                if (REM > 0) {
-                    bload<1>(rq_in, hofr[tt], &hw[tt][W]);
-                    bload<1>(rp_in, hofr[tt], &hp[tt][W]);
-                }
-            }
-        }
-#pragma unroll
-        for (int jj = 0; jj < OWN_R; ++jj) {
-            const int j = rd * OWN_R + jj;
-            float pn[KS], xn[KS];
-#pragma unroll
-            for (int s2 = 0; s2 < KS; ++s2) {
-                if (ITER) {
-                    zn[j][s2] = zv[jj][s2] - alpha * wv0[jj][s2];
-                    pn[s2] = zn[j][s2] + beta * pv0[jj][s2];
-                    xn[s2] = xv[jj][s2] + alpha * pv0[jj][s2];
-                } else {
-                    zn[j][s2] = 0.0f;
-                    pn[s2] = zv[jj][s2];
-                }
-            }
-            put_row(64 * wave + 16 * j + col, pn);
-            if (ITER) {
-                bstore<W>(rx, off[jj], xn);
-                if (REM > 0) bstore<1>(rx, offr[jj], &xn[W]);
-            }
-        }
-#pragma unroll
-        for (int tt = 0; tt < HAL_R; ++tt) {
-            const int t = rd * HAL_R + tt;
-            if (!(t < CYC_HT && wave + CYC_W * t < nht)) continue;
-            float hn[KS];
-#pragma unroll
-            for (int s2 = 0; s2 < KS; ++s2) hn[s2] = ITER ? (hz[tt][s2] - alpha * hw[tt][s2]) + beta * hp[tt][s2] : hz[tt][s2];
-            put_row(CYC + 16 * (wave + CYC_W * t) + col, hn);
-        }
-    }
-    __syncthreads();
-    // ---- phase 2: q = A p block by block over the four tiles (the next
-    // block's operands in flight), then w = M^-1 q, r = M z, stores, dots
-    f4 acc[CYC_T][MT];
-#pragma unroll
-    for (int j = 0; j < CYC_T; ++j)
-#pragma unroll
-        for (int i = 0; i < MT; ++i) acc[j][i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        if (k < 4) ops_load<NBP>(Ab, lane, (k + 1) * NBP, ablk[(k + 1) & 1]);
-#pragma unroll
-        for (int j = 0; j < CYC_T; ++j) {
-            const int r = k == 0 ? 64 * wave + 16 * j + col : (vc[j] ? (int)sl[j][k - 1] : -1);
-            float bv[KS];
-            if (r >= 0) {
-                const float* row = rowsL + r * N;
-                lds_get<W>(row, kk, bv);
-                if (REM > 0) bv[W] = kk < REM ? row[4 * W + kk] : 0.0f;
-            } else {
-#pragma unroll
-                for (int s2 = 0; s2 < KS; ++s2) bv[s2] = 0.0f;
-            }
-            // absent columns (past the end of the mesh) hold zero rows
-            mfma_block<KS, MT>(ablk[k & 1], bv, true, acc[j]);
-        }
-    }
-    const Rsrc rq_out = make_rsrc(q_out, vbytes), rr_out = make_rsrc(r_out, vbytes), rp_out = make_rsrc(p_out, vbytes);
-    double d[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    float a0[NBP], ainv[NBP];
-    if (ITER && precond) {
-        ops_load<NBP>(Ab, lane, 0, a0);
-        ops_load<NBP>(Ab, lane, 5 * NBP, ainv);
-    }
-#pragma unroll
-    for (int j = 0; j < CYC_T; ++j) {
-        uint32_t off, offr;
-        row_off(vc[j] ? el[j] : -1, off, offr);
-        float accs[KS], o[KS];
-#pragma unroll
-        for (int s2 = 0; s2 < KS; ++s2) {
-            accs[s2] = acc[j][s2 / 4][s2 % 4];
-            o[s2] = cscale * accs[s2];
-        }
-        if (!ITER) {
-            bstore<W>(rq_out, off, o);
-            if (REM > 0) bstore<1>(rq_out, offr, &o[W]);
-            continue;
-        }
-        float pn[KS];
-        {
-            const float* row = rowsL + (64 * wave + 16 * j + col) * N;
-            lds_get<W>(row, kk, pn);
-            if (REM > 0) pn[W] = kk < REM ? row[4 * W + kk] : 0.0f;
-        }
-        float wv[KS], rr[KS];
-        if (precond) {
-            f4 aw[MT], ar[MT];
-#pragma unroll
-            for (int i = 0; i < MT; ++i) {
-                aw[i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-                ar[i] = aw[i];
-            }
-            mfma_block<KS, MT>(ainv, accs, true, aw);
-            mfma_block<KS, MT>(a0, zn[j], true, ar);
-#pragma unroll
-            for (int s2 = 0; s2 < KS; ++s2) {
-                wv[s2] = aw[s2 / 4][s2 % 4];
-                rr[s2] = cscale * ar[s2 / 4][s2 % 4];
-            }
-        } else {
-#pragma unroll
-            for (int s2 = 0; s2 < KS; ++s2) {
-                wv[s2] = o[s2];
-                rr[s2] = zn[j][s2];
-            }
-        }
-        bstore<W>(rq_out, off, wv);
-        bstore<W>(rr_out, off, zn[j]);
-        bstore<W>(rp_out, off, pn);
-        if (REM > 0) {
-            bstore<1>(rq_out, offr, &wv[W]);
-            bstore<1>(rr_out, offr, &zn[j][W]);
-            bstore<1>(rp_out, offr, &pn[W]);
-        }
-        // partial dot products of the own rows in FP64 (absent rows hold zeros)
-#pragma unroll
-        for (int s2 = 0; s2 < KS; ++s2) {
-            const double pd = pn[s2], qd = o[s2], zd = zn[j][s2], wd = wv[s2], rd = rr[s2];
-            d[0] += pd * qd;
-            d[1] += qd * zd;
-            d[2] += qd * wd;
-            d[3] += rd * zd;
-            d[4] += rd * rd;
-        }
-    }
-    if (!ITER) return;
-    const double w4 = wave_total4(d[0], d[1], d[2], d[3]);
-    const double w5 = wave_sum(d[4]);
-    if (col == 0) sh[NPART * wave + kk] = w4;
-    if (lane == 0) sh[NPART * wave + 4] = w5;
-    __syncthreads();
-    if (threadIdx.x < NPART) {
-        double t = 0.0;
-#pragma unroll
-        for (int wv = 0; wv < CYC_W; ++wv) t += sh[wv * NPART + threadIdx.x];
-        part_out[PSTRIDE * blockIdx.x + threadIdx.x] = t;
-    }
-}
-
-int64_t cyc_blocks(const stdg_mesh* m) { return (m->d.cyc_chunks * m->G + 7) / 8 * 8; }
-
-// Measured on MI355X (rocprofv3, 663,552- and 82,944-element cubes, p = 3):
-// the cycle-staged iteration wins for one time node (166.5 vs 172.3 us per
-// launch) and loses for two (47.1 vs 44.0 us); the plain operator is faster
-// per tile (52.3 vs 63.9 us) with its own-class LDS operands.
-bool cyc_used(const stdg_mesh* m, bool iter) { return iter && m->d.cyc_hmax > 0 && m->G == 1; }
-
 // grid of the per-tile kernel k_cg_op: a multiple of the 8 XCDs
 int64_t tile_blocks(const stdg_mesh* m) {
     const int64_t waves = (m->E + 15) / 16 * m->G;
     return ((waves + WPB - 1) / WPB + 7) / 8 * 8;
 }
-
-size_t cyc_lds_bytes(const stdg_mesh* m) { return (size_t)(CYC + m->d.cyc_hmax) * m->N * sizeof(float); }
 
 int64_t prec_blocks(const stdg_mesh* m) {
     const int64_t waves = (m->E + 15) / 16 * m->G;
@@ -835,12 +521,9 @@ hipError_t op_n(const stdg_mesh* m, float* x, const float* r_in, const float* p_
                 float* p_out, float* q_out, const double* ab, float cscale, int precond, double* part_out,
                 hipStream_t s) {
     const uint32_t vbytes = (uint32_t)(4 * m->E * m->G * m->N);
-    if (cyc_used(m, ITER)) {
-        hipLaunchKernelGGL((k_cg_cyc<N, ITER>), dim3((unsigned)cyc_blocks(m)), dim3(64 * CYC_W), cyc_lds_bytes(m), s,
-                           m->d.cyc_aop, m->d.cls, m->d.cyc_slot, m->d.cyc_halo, m->d.cyc_hmax, m->d.cyc_chunks, x,
-                           r_in, p_in, q_in, r_out, p_out, q_out, ab, cscale, precond, (int32_t)m->E,
-                           (int32_t)m->G, vbytes, part_out);
-        return hipGetLastError();
+    if (lane_supported(m)) {
+        if (ITER) return lane_iter_f32(m, x, r_in, p_in, q_in, r_out, p_out, q_out, ab, cscale, precond, part_out, s);
+        return lane_apply_f32(m, r_in, q_out, cscale, s);
     }
     hipLaunchKernelGGL((k_cg_op<N, ITER>), dim3((unsigned)tile_blocks(m)), dim3(64 * WPB), 0, s, m->d.aop32, m->d.cls,
                        m->d.nbr, x, r_in, p_in, q_in, r_out, p_out, q_out, ab, cscale, precond, (int32_t)m->E,
@@ -848,10 +531,13 @@ hipError_t op_n(const stdg_mesh* m, float* x, const float* r_in, const float* p_
     return hipGetLastError();
 }
 
-template <int N> bool cg_operands(const stdg_mesh* m, std::vector<float>& out) {
+// Operands of k_cg_op per lane; invs receives the inverse own block of every
+// class ([n_classes][N][N], zeros unless every own block is SPD).
+template <int N> bool cg_operands(const stdg_mesh* m, std::vector<float>& out, std::vector<double>& invs) {
     typedef SliceShape<N> S;
     constexpr int W = S::W, REM = S::REM, KS = S::KS, MT = S::MT, NB = S::NB, NA = S::NA, NT = S::NT;
     out.assign((size_t)m->n_classes * 64 * NT, 0.0f);
+    invs.assign((size_t)m->n_classes * N * N, 0.0);
     bool spd = true;
     for (int c = 0; c < m->n_classes; ++c) {
         // the own block and its inverse (the block must be SPD for CG)
@@ -863,6 +549,7 @@ template <int N> bool cg_operands(const stdg_mesh* m, std::vector<float>& out) {
                 sym = sym && std::fabs(B0[i * N + j] - B0[j * N + i]) <=
                                  1e-12 * (std::fabs(B0[i * N + i]) + std::fabs(B0[j * N + j]));
         if (!sym || !cholesky(N, chol) || !lu_inverse(N, inv)) spd = false;
+        for (int i = 0; i < N * N; ++i) invs[(size_t)c * N * N + i] = (double)inv[i];
         auto entry = [&](int l, int v) -> float& { return out[(((size_t)c * (NT / 4) + v / 4) * 64 + l) * 4 + v % 4]; };
         for (int l = 0; l < 64; ++l) {
             // lane l supplies row l % 16 of each 16 x 4 A tile and contraction
@@ -881,70 +568,8 @@ template <int N> bool cg_operands(const stdg_mesh* m, std::vector<float>& out) {
                 }
         }
     }
+    if (!spd) std::fill(invs.begin(), invs.end(), 0.0);
     return spd;
-}
-
-// Slot and halo tables of the cycle-staged kernel.  Used when every
-// 64-element run holds one class (the class-chunked order of a mesh with
-// few geometry classes) and a chunk's rows fit the LDS budget; otherwise
-// the per-tile kernel k_cg_op serves the mesh.
-template <int N> int upload_cycle_tables(stdg_mesh* m, const std::vector<float>& aop) {
-    typedef SliceShape<N> S;
-    constexpr int NB = S::NB, NA = S::NA, NT = S::NT, NBP = (NB + 3) / 4 * 4;
-    const int64_t E = m->E;
-    for (int64_t t0 = 0; t0 < E; t0 += 64)
-        for (int64_t e = t0 + 1; e < std::min<int64_t>(t0 + 64, E); ++e)
-            if (m->cls[e] != m->cls[t0]) return STDG_OK;
-    const int64_t chunks = (E + CYC - 1) / CYC;
-    std::vector<int16_t> slot((size_t)E * 4, -1);
-    std::vector<std::vector<int32_t>> halos((size_t)chunks);
-    size_t hmax = 0;
-    std::vector<int32_t> where((size_t)E, -1);    // halo index of an element within the current chunk
-    for (int64_t c = 0; c < chunks; ++c) {
-        const int64_t lo = c * CYC, hi = std::min<int64_t>(lo + CYC, E);
-        auto& hl = halos[(size_t)c];
-        for (int64_t e = lo; e < hi; ++e)
-            for (int f = 0; f < 4; ++f) {
-                const int32_t nb = m->nbr[(size_t)e * 4 + f];
-                if (nb < 0) continue;
-                if (nb >= lo && nb < hi) {
-                    slot[(size_t)e * 4 + f] = (int16_t)(nb - lo);
-                    continue;
-                }
-                if (where[(size_t)nb] < 0) {
-                    where[(size_t)nb] = (int32_t)hl.size();
-                    hl.push_back(nb);
-                }
-                slot[(size_t)e * 4 + f] = (int16_t)(CYC + where[(size_t)nb]);
-            }
-        for (int32_t g : hl) where[(size_t)g] = -1;
-        hmax = std::max(hmax, hl.size());
-    }
-    hmax = (hmax + 15) / 16 * 16;
-    if (hmax > (size_t)CYC_HT * CYC_W * 16 || (CYC + hmax) * (size_t)m->N * sizeof(float) > 65536) return STDG_OK;
-    std::vector<int32_t> hflat((size_t)chunks * std::max<size_t>(hmax, 16), -1);
-    for (int64_t c = 0; c < chunks; ++c)
-        std::copy(halos[(size_t)c].begin(), halos[(size_t)c].end(), hflat.begin() + (size_t)c * hmax);
-    // the operand table re-laid per block: [class][6][NBP / 4][64][4], block
-    // 5 the inverse of the own block
-    std::vector<float> ab((size_t)m->n_classes * 6 * NBP * 64, 0.0f);
-    for (int c = 0; c < m->n_classes; ++c)
-        for (int blk = 0; blk < 6; ++blk)
-            for (int l = 0; l < 64; ++l)
-                for (int v = 0; v < NB; ++v) {
-                    const int src = blk < 5 ? blk * NB + v : NA + v;
-                    ab[(((size_t)c * 6 + blk) * (NBP / 4) + v / 4) * 256 + (size_t)l * 4 + v % 4] =
-                        aop[(((size_t)c * (NT / 4) + src / 4) * 64 + l) * 4 + src % 4];
-                }
-    STDG_HIP(hipMalloc(&m->d.cyc_aop, ab.size() * sizeof(float)));
-    STDG_HIP(hipMemcpy(m->d.cyc_aop, ab.data(), ab.size() * sizeof(float), hipMemcpyHostToDevice));
-    STDG_HIP(hipMalloc(&m->d.cyc_slot, slot.size() * sizeof(int16_t)));
-    STDG_HIP(hipMemcpy(m->d.cyc_slot, slot.data(), slot.size() * sizeof(int16_t), hipMemcpyHostToDevice));
-    STDG_HIP(hipMalloc(&m->d.cyc_halo, hflat.size() * sizeof(int32_t)));
-    STDG_HIP(hipMemcpy(m->d.cyc_halo, hflat.data(), hflat.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    m->d.cyc_hmax = (int)hmax;
-    m->d.cyc_chunks = chunks;
-    return STDG_OK;
 }
 
 }  // namespace
@@ -956,25 +581,24 @@ bool cg_fused_supported(const stdg_mesh* m) {
 
 int upload_cg_operands(stdg_mesh* m) {
     std::vector<float> t;
+    std::vector<double> invs;
     bool spd = false;
     switch (m->N) {
-        case 4: spd = cg_operands<4>(m, t); break;
-        case 10: spd = cg_operands<10>(m, t); break;
-        case 20: spd = cg_operands<20>(m, t); break;
+        case 4: spd = cg_operands<4>(m, t, invs); break;
+        case 10: spd = cg_operands<10>(m, t, invs); break;
+        case 20: spd = cg_operands<20>(m, t, invs); break;
         default: return STDG_OK;        // no fused kernel for this degree
     }
     m->d.cg_precond_ok = spd ? 1 : 0;
     STDG_HIP(hipMalloc(&m->d.aop32, t.size() * sizeof(float)));
     STDG_HIP(hipMemcpy(m->d.aop32, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
-    switch (m->N) {
-        case 4: return upload_cycle_tables<4>(m, t);
-        case 10: return upload_cycle_tables<10>(m, t);
-        default: return upload_cycle_tables<20>(m, t);
-    }
+    return upload_lane_operands(m, invs);
 }
 
 // workgroups (and partial records) of one CG iteration launch
-int64_t cg_op_blocks(const stdg_mesh* m) { return cyc_used(m, true) ? cyc_blocks(m) : tile_blocks(m); }
+int64_t cg_op_blocks(const stdg_mesh* m) {
+    return lane_supported(m) ? lane_iter_blocks(m) : tile_blocks(m);
+}
 
 int64_t cg_partial_len(const stdg_mesh* m) { return PSTRIDE * cg_op_blocks(m); }
 
@@ -1004,6 +628,7 @@ hipError_t launch_cg_apply_f32(const stdg_mesh* m, const float* x, float* y, flo
 }
 
 hipError_t launch_cg_prec_f32(const stdg_mesh* m, const float* x, float* y, float scale, hipStream_t s) {
+    if (lane_supported(m)) return lane_prec_f32(m, x, y, scale, s);
     const uint32_t vbytes = (uint32_t)(4 * m->E * m->G * m->N);
 #define STDG_OPN(n)                                                                                            \
     case n:                                                                                                    \

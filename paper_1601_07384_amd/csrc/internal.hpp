@@ -35,13 +35,13 @@ struct DeviceTables {
     float* blocks32 = nullptr;    // same, FP32
     float* aop32 = nullptr;       // FP32 blocks per lane in MFMA operand order (fused CG kernel)
     int cg_precond_ok = 0;        // every own block SPD: block-Jacobi operands in aop32
-    // cycle-staged CG kernel (one workgroup per chunk of CG_CYC consecutive
-    // elements and time node; 0 = not used for this mesh)
-    float* cyc_aop = nullptr;     // class operands laid out per block (cycle-staged kernel)
-    int16_t* cyc_slot = nullptr;  // [E][4] LDS row of the neighbour across local face f, -1 none
-    int32_t* cyc_halo = nullptr;  // [chunks][cyc_hmax] element of halo row h, -1 padding
-    int cyc_hmax = 0;             // halo rows per chunk (multiple of 16)
-    int64_t cyc_chunks = 0;
+    // chunk-staged CG iteration (one workgroup per chunk of 384 consecutive
+    // elements and time node; chunk_hmax = 0: not used for this mesh)
+    int16_t* chunk_slot = nullptr;  // [E][4] LDS row of the neighbour across local face f, -1 none
+    int32_t* chunk_halo = nullptr;  // [chunks][chunk_hmax] element of halo row h, -1 padding
+    int chunk_hmax = 0;             // halo rows per chunk (multiple of 64)
+    int64_t chunk_chunks = 0;
+    float* lane_ops = nullptr;    // class operands of the element-per-lane kernels (null: a run mixes classes)
     int32_t* cls = nullptr;       // [E]
     int32_t* nbr = nullptr;       // [E][4]  -1 on a boundary face
     double* C = nullptr;          // [G][G]  time factor W T^-1 W

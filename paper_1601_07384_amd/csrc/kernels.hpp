@@ -29,6 +29,18 @@ hipError_t launch_cg_prec_f32(const stdg_mesh* m, const float* x, float* y, floa
 hipError_t launch_cg_apply_f32(const stdg_mesh* m, const float* x, float* y, float cscale, hipStream_t s);
 hipError_t launch_cg_tail_f32(float* x, const float* p, int64_t n, const double* part, int64_t n_part, double* ab,
                               hipStream_t s);
+bool lane_supported(const stdg_mesh* m);
+int upload_lane_operands(stdg_mesh* m, const std::vector<double>& inv);
+int64_t lane_iter_blocks(const stdg_mesh* m);
+hipError_t lane_iter_f32(const stdg_mesh* m, float* x, const float* r_in, const float* p_in, const float* q_in,
+                         float* r_out, float* p_out, float* q_out, const double* ab, float cscale, int precond,
+                         double* part_out, hipStream_t s);
+hipError_t lane_apply_f32(const stdg_mesh* m, const float* x, float* y, float cscale, hipStream_t s);
+hipError_t lane_prec_f32(const stdg_mesh* m, const float* x, float* y, float scale, hipStream_t s);
+int64_t lane_len(const stdg_mesh* m);   // floats of a run-layout vector
+hipError_t lane_pack(const stdg_mesh* m, const double* x, double scale, float* y, hipStream_t s);
+hipError_t lane_unpack(const stdg_mesh* m, const float* y, const double* M, double scale, bool add, double* x,
+                       hipStream_t s);
 hipError_t launch_cg_check_f32(const double* part, int64_t n_part, double* scal, int slot, hipStream_t s);
 hipError_t time_mix_f64(const stdg_mesh* m, const double* M, const double* x, double* y, hipStream_t s);
 hipError_t time_mix_f32(const stdg_mesh* m, const float* M, const float* x, float* y, hipStream_t s);

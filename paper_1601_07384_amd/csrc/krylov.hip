@@ -357,6 +357,7 @@ struct Ctx {
     int applies = 0;
     double loop_ms = 0.0;    // device time of the one-kernel CG iterations (HIP events)
     int loop_iters = 0;
+    bool run_layout = false; // FP32 vectors in the run layout of the element-per-lane kernels (n padded)
 };
 
 template <typename T> struct Apply;
@@ -378,6 +379,10 @@ template <> struct Apply<double> {
 };
 template <> struct Apply<float> {
     static hipError_t run(const Ctx& c, const float* x, float* y) {
+        if (c.run_layout) {
+            if (c.op != 0 && c.op != 2) return hipErrorInvalidValue;
+            return lane_apply_f32(c.m, x, y, c.op == 2 ? 1.0f : (float)c.m->Ctime[0], c.s);
+        }
         if (c.op == 0) return launch_apply_f32(c.m, x, y, c.s);
         if (c.op == 2) return launch_apply_f32_c(c.m, c.m->d.Cid32, x, y, c.s);
         return hipErrorInvalidValue;
@@ -791,8 +796,10 @@ int ensure_workspace(stdg_mesh* m, int mres, bool need32) {
         STDG_HIP(hipHostMalloc(&w.hscal, sizeof(double) * 8));
     }
     if (need32) {
+        // long enough for the run layout as well (padded to whole 64-element runs)
+        const size_t n32 = std::max<size_t>(n, (size_t)lane_len(m));
         for (float** f : {&w.r32, &w.p32, &w.q32, &w.x32, &w.b32, &w.p32b, &w.r32b, &w.q32b})
-            if (!*f) STDG_HIP(hipMalloc(f, n * sizeof(float)));
+            if (!*f) STDG_HIP(hipMalloc(f, n32 * sizeof(float)));
         if (!w.ev[0])
             for (hipEvent_t& e : w.ev) STDG_HIP(hipEventCreate(&e));
     }
@@ -1042,6 +1049,8 @@ int solve_with(stdg_mesh* m, const double* b, double* x, const stdg_solve_opts& 
         if (status == STDG_OK && rel > o.rtol) status = STDG_NOT_CONVERGED;
     } else {
         // FP64 iterative refinement around FP32 Krylov solves
+        const bool run_inner = lane_supported(m) && (o.method == STDG_CG || o.method == STDG_CG_TIME) &&
+                               w.p32b && 2 * cg_partial_len(m) <= (int64_t)NBLK * 208;
         for (outer = 1; outer <= o.max_outer + 1; ++outer) {
             if (int e = check(rel)) return e;
             if (outer == 1) rel0 = rel;
@@ -1060,19 +1069,38 @@ int solve_with(stdg_mesh* m, const double* b, double* x, const stdg_solve_opts& 
             // r / |r| (FP32 vectors and products then stay far from the ends
             // of the FP32 range whatever the scale of the problem) and the
             // correction scaled back by |r|
-            hipLaunchKernelGGL(k_d2f_scaled, dim3(gb), dim3(256), 0, c.s, w.r, w.b32, 1.0 / rn, n);
-            hipLaunchKernelGGL(k_fill<float>, dim3(gb), dim3(256), 0, c.s, w.x32, 0.0f, n);
             int it = 0;
             double res = 0.0;
             // each inner solve reduces the residual by inner_rtol, but never
             // further than the final tolerance needs (a good initial guess
             // then saves inner iterations instead of overshooting)
             const double inner_abs = std::max(o.inner_rtol * rn, 0.25 * o.rtol * bnorm);
-            status = run_krylov<float>(c, o.method, w.b32, w.x32, w.r32, w.p32, w.q32, w.V32, mres,
-                                       inner_abs / rn, o.max_iter - inner_total, o.check_every, it, res);
-            inner_total += it;
-            if (status < 0) return status;
-            hipLaunchKernelGGL(k_add_f32, dim3(gb), dim3(256), 0, c.s, x, w.x32, rn, n);
+            if (run_inner) {
+                // element-per-lane kernels: CG on c B (STDG_CG) or on B (x) I
+                // (STDG_CG_TIME, correction (I (x) C^-1) w) in the run layout
+                const int64_t n32 = lane_len(m);
+                CK(lane_pack(m, w.r, 1.0 / rn, w.b32, c.s));
+                hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n32)), dim3(256), 0, c.s, w.x32, 0.0f, n32);
+                c.n = n32;
+                c.run_layout = true;
+                c.op = o.method == STDG_CG ? 0 : 2;
+                status = cg<float>(c, w.b32, w.x32, w.r32, w.p32, w.q32, inner_abs / rn, o.max_iter - inner_total,
+                                   o.check_every, it, res);
+                c.n = n;
+                c.run_layout = false;
+                c.op = 0;
+                inner_total += it;
+                if (status < 0) return status;
+                CK(lane_unpack(m, w.x32, o.method == STDG_CG ? nullptr : m->d.Cinv, rn, true, x, c.s));
+            } else {
+                hipLaunchKernelGGL(k_d2f_scaled, dim3(gb), dim3(256), 0, c.s, w.r, w.b32, 1.0 / rn, n);
+                hipLaunchKernelGGL(k_fill<float>, dim3(gb), dim3(256), 0, c.s, w.x32, 0.0f, n);
+                status = run_krylov<float>(c, o.method, w.b32, w.x32, w.r32, w.p32, w.q32, w.V32, mres,
+                                           inner_abs / rn, o.max_iter - inner_total, o.check_every, it, res);
+                inner_total += it;
+                if (status < 0) return status;
+                hipLaunchKernelGGL(k_add_f32, dim3(gb), dim3(256), 0, c.s, x, w.x32, rn, n);
+            }
             CK(hipGetLastError());
         }
         outer = std::min(outer, o.max_outer);
@@ -1185,7 +1213,44 @@ extern "C" int stdg_pressure_solve_noalloc(const stdg_mesh* cm, const double* b,
     return solve_with(m, b, x, o, mres, rep, stream, w, t0);
 }
 
-// y = (B (x) I) x in FP32 with the CG operator kernel.
+namespace stdg {
+namespace {
+__global__ void k_f2d_scaled(const float* __restrict__ a, double* __restrict__ b, double scale, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = scale * (double)a[i];
+}
+}  // namespace
+}  // namespace stdg
+
+extern "C" int stdg_inner_from_f64(const stdg_mesh* m, const double* x, double scale, float* y, void* stream) {
+    if (!m || !x || !y) { set_error("null argument"); return STDG_ERR_ARG; }
+    if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
+    const hipStream_t s = (hipStream_t)stream;
+    if (lane_supported(m)) {
+        CK(lane_pack(m, x, scale, y, s));
+    } else {
+        const int64_t n = m->E * m->G * m->N;
+        hipLaunchKernelGGL(k_d2f_scaled, dim3(grid_for(n)), dim3(256), 0, s, x, y, scale, n);
+        CK(hipGetLastError());
+    }
+    return STDG_OK;
+}
+
+extern "C" int stdg_inner_to_f64(const stdg_mesh* m, const float* y, double scale, double* x, void* stream) {
+    if (!m || !x || !y) { set_error("null argument"); return STDG_ERR_ARG; }
+    if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
+    const hipStream_t s = (hipStream_t)stream;
+    if (lane_supported(m)) {
+        CK(lane_unpack(m, y, nullptr, scale, false, x, s));
+    } else {
+        const int64_t n = m->E * m->G * m->N;
+        hipLaunchKernelGGL(k_f2d_scaled, dim3(grid_for(n)), dim3(256), 0, s, y, x, scale, n);
+        CK(hipGetLastError());
+    }
+    return STDG_OK;
+}
+
+// y = (B (x) I) x in FP32 with the CG operator kernel (inner layout).
 extern "C" int stdg_pressure_apply_spatial_f32(const stdg_mesh* cm, const float* x, float* y, void* stream) {
     if (!cm || !x || !y) { set_error("null argument"); return STDG_ERR_ARG; }
     stdg_mesh* m = const_cast<stdg_mesh*>(cm);

@@ -123,27 +123,81 @@ def _time_factor_inverse(pg):
     return np.linalg.inv(W @ np.linalg.inv(Tc) @ W)
 
 
+def spatial_f32_via_inner(m, x):
+    """(B (x) I) x through the C ABI: x ([E, N_st] internal order, values
+    exact in FP32) moved to the inner layout, the FP32 operator, the result
+    moved back to [E, N_st] FP64."""
+    x64 = gpu(np.ascontiguousarray(x).ravel())
+    xf = torch.empty(m.inner_len, dtype=torch.float32, device=DEV)
+    yf = torch.full_like(xf, float("nan"))
+    m.inner_from_f64(x64, xf)
+    m.apply_spatial_f32(xf, yf)
+    y64 = torch.empty_like(x64)
+    m.inner_to_f64(yf, y64)
+    torch.cuda.synchronize()
+    if m.inner_len > m.E * m.Nst:           # slots of a ragged last run stay zero
+        assert torch.isfinite(yf).all()
+    return y64.cpu().numpy().reshape(m.E, m.Nst)
+
+
+def run_layout_index(E, G, N):
+    """Entry of the run layout holding (element e, time node a, value k), as
+    the header documents it: (((R G + a) (N / w) + k / w) 64 + l) w + k % w."""
+    w = 4 if N % 4 == 0 else (2 if N % 2 == 0 else 1)
+    e, a, k = np.meshgrid(np.arange(E), np.arange(G), np.arange(N), indexing="ij")
+    R, l = e // 64, e % 64
+    return (((R * G + a) * (N // w) + k // w) * 64 + l) * w + k % w
+
+
+@pytest.mark.parametrize("n,p,pg,periodic", [(4, 3, 1, True), (4, 2, 0, True), (4, 1, 1, True), (3, 2, 1, True),
+                                             (3, 3, 0, False)])
+def test_inner_layout_moves(n, p, pg, periodic):
+    """stdg_inner_from_f64 / stdg_inner_to_f64: the documented inner layout
+    (run layout on the periodic 4^3 cube, whose 64-element runs share a class;
+    element-major otherwise), scaling, zero padding, exact round trip of
+    FP32-exact values."""
+    X, T = kuhn_mesh(n) if periodic else case_mesh(n)
+    m = P.Mesh(X, T, p, pg, dt=1e-2, periodic=periodic)
+    run = n == 4
+    assert m.inner_layout == (P.STDG_LAYOUT_RUN if run else P.STDG_LAYOUT_ELEMENT)
+    x = np.random.default_rng(5).standard_normal((m.E, m.G, m.N)).astype(np.float32).astype(np.float64)
+    xf = torch.full((m.inner_len,), float("nan"), dtype=torch.float32, device=DEV)
+    m.inner_from_f64(gpu(x.ravel()), xf, scale=0.5)
+    y = xf.cpu().numpy()
+    if run:
+        assert m.inner_len == (m.E + 63) // 64 * 64 * m.Nst
+        idx = run_layout_index(m.E, m.G, m.N)
+        assert np.array_equal(y[idx], (0.5 * x).astype(np.float32))
+        pad = np.ones(m.inner_len, bool)
+        pad[idx.ravel()] = False
+        assert np.all(y[pad] == 0.0)
+    else:
+        assert m.inner_len == m.E * m.Nst
+        assert np.array_equal(y, (0.5 * x).astype(np.float32).ravel())
+    back = torch.empty(m.E * m.Nst, dtype=torch.float64, device=DEV)
+    m.inner_to_f64(xf, back, scale=2.0)
+    assert np.array_equal(back.cpu().numpy(), x.ravel())
+
+
 @pytest.mark.parametrize("n,p,pg", [(8, 3, 1), (48, 3, 0), (32, 2, 1), (24, 3, 1)])
 def test_spatial_apply_f32_sampled_rows(n, p, pg):
     """The FP32 spatial operator (B (x) I) of the time-decoupled inner solve on
-    periodic cubes whose 64-element runs share a class, so the cycle-staged
-    kernel runs with its halo rows (8^3: 8 chunks; the 663,552-, 196,608- and
-    82,944-element cubes at full size): sampled rows against the oracle's
-    S (I (x) C^-1) x, 1e-5 relative."""
+    periodic cubes whose 64-element runs share a class, so the element-per-lane
+    kernel runs in the run layout (the 663,552-, 196,608- and 82,944-element
+    cubes at full size): sampled rows against the oracle's S (I (x) C^-1) x,
+    1e-5 relative."""
     print(f"spatial f32 sampled n={n} p={p} pg={pg}", flush=True)
     dt = 1e-3
     X, T = kuhn_mesh(n)
     m = P.Mesh(X, T, p, pg, dt=dt, periodic=True)
+    assert m.inner_layout == P.STDG_LAYOUT_RUN
     ops = SpaceTimeOperators(OracleMesh(X, T, periodic=True), p, pg, dt)
     rng = np.random.default_rng(40 + n)
     x = rng.standard_normal((m.E, m.G, m.N)).astype(np.float32).astype(np.float64)
     xs = np.einsum("ab,ebn->ean", _time_factor_inverse(pg), x).reshape(m.E, m.Nst)
     perm = m.permutation()
-    xf = gpu(x.reshape(m.E, m.Nst)[perm].ravel(), torch.float32)
-    yf = torch.empty_like(xf)
-    m.apply_spatial_f32(xf, yf)
-    torch.cuda.synchronize()
-    yg = to_input(yf.cpu().numpy().astype(np.float64).reshape(m.E, m.Nst), perm)
+    yg = spatial_f32_via_inner(m, x.reshape(m.E, m.Nst)[perm])
+    yg = to_input(yg, perm)
     rows = np.concatenate([rng.choice(m.E, size=24, replace=False), [0, m.E - 1]])
     yo = apply_S(ops, xs, elements=rows)
     err = np.abs(yg[rows] - yo[rows]).max() / np.abs(yo[rows]).max()
@@ -389,9 +443,5 @@ def test_spatial_apply_f32_matches_oracle(n, p, pg, periodic):
     xs = np.einsum("ab,ebn->ean", Cinv, x)
     perm = m.permutation()
     yo = apply_S(ops, to_input(xs.reshape(m.E, m.Nst), perm))
-    xf = gpu(x.ravel(), torch.float32)
-    yf = torch.empty_like(xf)
-    m.apply_spatial_f32(xf, yf)
-    torch.cuda.synchronize()
-    yg = to_input(yf.cpu().numpy().astype(np.float64).reshape(m.E, m.Nst), perm)
+    yg = to_input(spatial_f32_via_inner(m, x.reshape(m.E, m.Nst)), perm)
     assert np.abs(yg - yo).max() <= 1e-5 * np.abs(yo).max()
