@@ -28,10 +28,12 @@ chosen (FP32 refinement PCG, learned guess), with ablations that change one
 thing at a time (precision, preconditioner, initial guess).
 
 The roofline entry is for the step's dominant kernel, the one-kernel FP32 CG
-iteration k_cg_op<N, true>.  Its per-launch duration is the library's own
-HIP-event measurement on its stream around the back-to-back iteration
-launches of the timed steps (stdg_step_report.pressure_fused_iter_us).
-Algorithmic bytes per launch: read z, p, w, x and write them once (8 x 4 B
+iteration (k_lane_chunk<N> on meshes whose 64-element runs share a geometry
+class, k_cg_op<N, true> otherwise), together with the one-block scalar kernel
+k_cg_red that precedes each launch.  Its duration per iteration is the
+library's own HIP-event measurement on its stream around the back-to-back
+iteration launches of the timed steps (stdg_step_report.pressure_fused_iter_us).
+Algorithmic bytes per iteration: read z, p, w, x and write them once (8 x 4 B
 per DoF) plus 20 B of indices per element.
 """
 
@@ -51,11 +53,11 @@ CONFIGS = {
     "c2": dict(n=24, p=3, pg=1, dt=1e-3, nu=1e-3, n_pic=2),
     "c5": dict(n=32, p=2, pg=1, dt=1e-3, nu=1e-3, n_pic=2),
 }
-# HBM bytes per launch of k_cg_op<20, true> on the 663,552-element cube from
+# HBM bytes per launch of k_lane_chunk<20> on the 663,552-element cube from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads
 # for a device copy of known size; valid only for the kernel source they were
 # measured on (sha256 prefix).  None until measured.
-MEASURED_TRAFFIC = {"source": "paper_1601_07384_amd/csrc/cg_fused.hip", "sha256": None, "bytes": None,
+MEASURED_TRAFFIC = {"source": "paper_1601_07384_amd/csrc/cg_lane.hip", "sha256": None, "bytes": None,
                     "config": "c3"}
 FP64_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
@@ -71,10 +73,17 @@ def parse():
     ap.add_argument("--applies", type=int, default=50, help="timed launches per operator (>= 20)")
     ap.add_argument("--no-ablation", action="store_true", help="skip the plain-form and ablation steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=256)
+    ap.add_argument("--cpu-rows", type=int, default=4096)
+    ap.add_argument("--cpu-cores", type=int, default=0, help="oracle worker processes (0: min(16, host cores))")
     ap.add_argument("--record", type=int, default=12, help="steps recorded to train the learned guess")
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--lr", type=float, default=3e-4)
+    ap.add_argument("--experiment", choices=["learned"], default=None,
+                    help="learned: the held-out initial-guess experiment (record and train on the first "
+                         "--train-steps steps, then compare the guesses on the next --eval-steps steps); "
+                         "prints its own JSON line instead of the benchmark line")
+    ap.add_argument("--train-steps", type=int, default=100)
+    ap.add_argument("--eval-steps", type=int, default=100)
     ap.add_argument("--jitter", type=float, default=0.0,
                     help="move interior vertices by up to this fraction of h: every element then "
                          "has its own geometry class (operator blocks streamed per element)")
@@ -104,31 +113,124 @@ def workload_label(c, jitter):
     return s
 
 
-def cpu_baseline(rows, X, T, c):
+def _oracle_rows(args):
+    """Worker: the oracle's operator rows `rows` (first call integrates their
+    face matrices, then `calls` timed calls); returns the call times."""
+    rows, calls = args
+    ts = []
+    apply_S(_ORACLE["ops"], _ORACLE["x"], elements=rows)
+    for _ in range(calls):
+        t0 = time.perf_counter()
+        apply_S(_ORACLE["ops"], _ORACLE["x"], elements=rows)
+        ts.append(time.perf_counter() - t0)
+    return ts
+
+
+_ORACLE = {}
+
+
+def cpu_baseline(rows, X, T, c, cores):
     """The FP64 oracle's operator on a bounded sample of rows of the same
-    mesh: a first call integrates the sample's face matrices (not timed),
-    then the median of five calls with those matrices cached."""
+    mesh, split over `cores` forked worker processes of the host: each worker
+    first integrates its rows' face matrices (not timed), then applies them
+    five times; the rate is the sample's values over the median of the
+    slowest worker's call times."""
+    import multiprocessing as mp
+    global apply_S
     from oracle.mesh import Mesh as OracleMesh
     from oracle.spacetime import SpaceTimeOperators
     from oracle.pressure import apply_S
     om = OracleMesh(X, T, periodic=True)
     ops = SpaceTimeOperators(om, c["p"], c["pg"], c["dt"])
-    x = np.random.default_rng(0).standard_normal((om.E, ops.Nst))
+    _ORACLE["ops"] = ops
+    _ORACLE["x"] = np.random.default_rng(0).standard_normal((om.E, ops.Nst))
     sample = np.linspace(0, om.E - 1, rows).astype(np.int64)
+    parts = [(part, 5) for part in np.array_split(sample, cores)]
     t0 = time.perf_counter()
-    apply_S(ops, x, elements=sample)
-    warm = time.perf_counter() - t0
-    ts = []
-    for _ in range(5):
-        t0 = time.perf_counter()
-        apply_S(ops, x, elements=sample)
-        ts.append(time.perf_counter() - t0)
-    t = float(np.median(ts))
-    return {"value": rows * ops.Nst / t / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": f"{rows} evenly spaced rows of the {om.E:,}-element Schur operator (literal "
-                      f"space-time matrices, extended precision, face matrices cached by a first call "
-                      f"of {warm:.1f} s), median of 5 calls: {t:.3f} s per call, single-threaded numpy",
+    with mp.get_context("fork").Pool(cores) as pool:
+        times = pool.map(_oracle_rows, parts)
+    wall = time.perf_counter() - t0
+    t = float(np.median(np.max(np.array(times), axis=0)))
+    return {"value": rows * ops.Nst / t / 1e9, "unit": "GDoF/s", "cores": cores, "kind": "oracle",
+            "sample": f"{rows} evenly spaced rows of the {om.E:,}-element Schur operator (literal space-time "
+                      f"matrices, extended-precision numpy), split over {cores} worker processes; each worker "
+                      f"integrates its rows' face matrices once, then applies them 5 times; median over the "
+                      f"calls of the slowest worker: {t:.3f} s per call ({wall:.1f} s in all)",
             "host_cores": os.cpu_count()}
+
+
+def learned_guess_experiment(args, P, torch, m, c, vhat, vbar, p, hist, opts, label):
+    """The learned initial guess on held-out steps.  Steps 1 .. T (T =
+    --train-steps) of the trajectory are recorded (right-hand side and
+    solution of each step's first pressure solve) and the model is trained on
+    them on the GPU; each of the next --eval-steps steps is then run from the
+    same state with the previous-step, the extrapolated and the learned start
+    of its first pressure solve (the trajectory continues with the learned
+    one), all with the chosen solver (FP32 refinement PCG to 1e-10)."""
+    n = m.E * m.Nst
+    T = args.train_steps
+    Xr = torch.zeros(T * n, dtype=torch.float64, device="cuda:0")
+    Br = torch.zeros(T * n, dtype=torch.float64, device="cuda:0")
+    t0 = time.perf_counter()
+    for k in range(T):
+        m.picard_step(vhat, vbar, p, None,
+                      opts=opts(P.STDG_KRYLOV_EXTRAPOLATE, rec=(Br[k * n:(k + 1) * n], Xr[k * n:(k + 1) * n])))
+    torch.cuda.synchronize()
+    record_s = time.perf_counter() - t0
+    progress(f"recorded {T} steps: {record_s:.1f} s")
+    model = P.Model(m, hidden=128, precision=P.STDG_FP32, batch=m.E, lr=args.lr, seed=1601,
+                    loss=P.STDG_LOSS_RESIDUAL)
+    S = T - 2
+    train = model.train(Xr[n:(T - 1) * n], Xr[:S * n], Br[2 * n:], Xr[2 * n:], epochs=args.epochs)
+    del Xr, Br
+    torch.cuda.empty_cache()
+    progress(f"trained on {S} steps: {train.seconds:.1f} s, loss {train.first_loss:.3g} -> {train.last_loss:.3g}")
+    guesses = [("previous", P.STDG_KRYLOV_PREVIOUS), ("extrapolated", P.STDG_KRYLOV_EXTRAPOLATE),
+               ("learned", P.STDG_KRYLOV_LEARNED)]
+    res = {g: {"first_iters": [], "first_s": [], "step_iters": [], "step_pressure_s": [], "r0": []}
+           for g, _ in guesses}
+    weights = []
+    max_diff = 0.0
+    for step in range(args.eval_steps):
+        state = (vhat.clone(), vbar.clone(), p.clone(), hist.clone())
+        out = {}
+        for g, kg in guesses:
+            vh, vb, pp, hh = (t.clone() for t in state)
+            r = m.picard_step(vh, vb, pp, None, opts=opts(kg, model=model if g == "learned" else None, h=hh))
+            torch.cuda.synchronize()
+            d = res[g]
+            d["first_iters"].append(r.first_pressure_iters)
+            d["first_s"].append(r.first_pressure_seconds)
+            d["step_iters"].append(r.pressure_iters)
+            d["step_pressure_s"].append(r.pressure_seconds)
+            d["r0"].append(r.first_initial_residual)
+            if g == "learned":
+                weights.append(r.guess_weight_network)
+            out[g] = (vh, vb, pp, hh)
+        pl = out["learned"][2]
+        for g in ("previous", "extrapolated"):
+            max_diff = max(max_diff, float((out[g][2] - pl).abs().max() / pl.abs().max()))
+        vhat.copy_(out["learned"][0]); vbar.copy_(out["learned"][1]); p.copy_(pl); hist.copy_(out["learned"][3])
+        del out, state
+        if (step + 1) % 10 == 0:
+            progress(f"held-out step {step + 1}: first-solve iterations " +
+                     ", ".join(f"{g} {sum(res[g]['first_iters'])}" for g, _ in guesses))
+    summary = {g: {"first_solve_iters": int(sum(d["first_iters"])), "first_solve_s": float(sum(d["first_s"])),
+                   "step_pressure_iters": int(sum(d["step_iters"])),
+                   "step_pressure_s": float(sum(d["step_pressure_s"])),
+                   "mean_first_initial_rel_residual": float(np.mean(d["r0"]))} for g, d in res.items()}
+    le, ex = summary["learned"]["first_solve_iters"], summary["extrapolated"]["first_solve_iters"]
+    print(json.dumps({
+        "metric": "first pressure-solve iterations and time to 1e-10 on held-out steps, by initial guess",
+        "config": {"workload": label, "train_steps": T, "eval_steps": args.eval_steps, "epochs": args.epochs,
+                   "lr": args.lr, "solver": "FP32-inner block-Jacobi PCG in FP64 refinement, rtol 1e-10"},
+        "by_guess": summary,
+        "learned_vs_extrapolated_first_iters": le / ex if ex else None,
+        "network_beats_extrapolation": le < ex,
+        "mean_network_weight": float(np.mean(weights)) if weights else None,
+        "max_pressure_rel_diff_between_guesses": max_diff,
+        "train": {"samples": train.samples, "seconds": train.seconds, "loss_first_epoch": train.first_loss,
+                  "loss_last_epoch": train.last_loss, "record_s": record_s}}))
 
 
 def progress(msg):
@@ -153,6 +255,7 @@ def main():
     progress(f"mesh built: {build_s:.1f} s ({m.E} elements, {m.n_classes} geometry classes)")
     perm = m.permutation()
     E, G, N, Nst = m.E, m.G, m.N, m.Nst
+    run_layout = m.inner_layout == P.STDG_LAYOUT_RUN
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     # initial state: nodal Fourier field (constant over the slab), its dual projection
@@ -178,6 +281,10 @@ def main():
         return P.step_opts(n_picard=n_pic, pressure=pressure or press, viscous=visc, krylov_guess=kg,
                            model=model, hist=hist if h is None else h,
                            rec_b=rec[0] if rec else None, rec_x=rec[1] if rec else None)
+
+    if args.experiment == "learned":
+        learned_guess_experiment(args, P, torch, m, c, vhat, vbar, p, hist, opts, workload_label(c, args.jitter))
+        return
 
     # ---- trajectory for the learned guess: record the first pressure solve of
     # each step (right-hand side and solution), then train on the GPU
@@ -299,8 +406,9 @@ def main():
         "dtype": "f32 inner operator, f64 refinement", "data": "synthetic",
         "config": {"workload": workload_label(c, args.jitter), "pressure_dof": dofs,
                    "geometry_classes": m.n_classes},
-        "operator": {"kernel": f"k_cg_op<{N},false> (FP32 B (x) I on MFMA)" if op32 is not None
-                     else "FP64 S x", "median_us": inner_us, "launches": args.applies,
+        "operator": {"kernel": (f"{'k_lane_op' if run_layout else 'k_cg_op'}<{N}> (FP32 B (x) I on MFMA)"
+                                if op32 is not None else "FP64 S x"), "median_us": inner_us,
+                     "launches": args.applies,
                      "fp64_apply": {"median_us": fp64_us, "gdofs": dofs / fp64_us / 1e3,
                                     "tflops": flops / fp64_us / 1e6,
                                     "frac_fp64_peak": flops / fp64_us / 1e6 / FP64_PEAK_TFLOPS}},
@@ -318,7 +426,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": k_bytes / k_s / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": k_bytes / k_s / 1e9 / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.config) if args.jitter == 0 else None,
-                     "kernel": f"k_cg_op<{N},true> (one PCG iteration)", "kernel_us": it_us,
+                     "kernel": (f"k_lane_chunk<{N}> + k_cg_red (one PCG iteration)" if run_layout
+                                else f"k_cg_op<{N},true> + k_cg_red (one PCG iteration)"), "kernel_us": it_us,
                      "kernel_launches": sum(r.pressure_iters for r in reps),
                      "bytes_per_launch": k_bytes, "flops_per_launch": k_flops,
                      "mfma_tflops": k_flops / k_s / 1e12,
@@ -330,7 +439,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         progress("oracle sample on the host")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_rows, X, T, c)
+        cores = args.cpu_cores or min(16, os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_rows, X, T, c, cores)
     print(json.dumps(out))
 
 

@@ -101,8 +101,9 @@ typedef struct {
 
 /* Layouts of FP32 vectors of the inner (refinement) solve.
  * STDG_LAYOUT_ELEMENT: [E][G][N] like every FP64 vector.
- * STDG_LAYOUT_RUN (meshes whose consecutive 64-element runs each hold one
- * geometry class, e.g. the class-chunked Kuhn cubes): value k of element
+ * STDG_LAYOUT_RUN (p = 1, 2, 3 on meshes whose consecutive 64-element runs
+ * each hold one geometry class, e.g. the class-chunked Kuhn cubes; p = 4 on
+ * meshes whose runs hold at most 1.5 classes on average): value k of element
  * e = 64 R + l at time node a is entry (((R G + a) (N / w) + k / w) 64 + l) w
  * + k % w with w = 4 if 4 divides N, else 2 if 2 does, else 1; the length is
  * ceil(E / 64) 64 G N and the entries of the missing elements of a ragged
@@ -206,8 +207,11 @@ typedef struct {
  * operator of the time-decoupled solve (STDG_CG_TIME) and, times the scalar
  * C, of the p_gamma = 0 solve.  x, y: device floats in the mesh's inner
  * layout (stdg_mesh_info.inner_layout, inner_len entries), 16-byte aligned,
- * not overlapping.  Runs the FP32 MFMA kernel of the fused CG iteration
- * (p = 1, 2, 3; STDG_ERR_ARG otherwise).  Asynchronous. */
+ * not overlapping.  Runs an FP32 MFMA kernel: the element-per-lane kernel
+ * when the inner layout is STDG_LAYOUT_RUN (p = 1, 2, 3 on meshes whose
+ * 64-element runs each hold one geometry class; p = 4 on meshes whose runs
+ * mostly do), the tile kernel of the fused CG iteration otherwise (p = 1, 2,
+ * 3); STDG_ERR_ARG when neither applies.  Asynchronous. */
 int stdg_pressure_apply_spatial_f32(const stdg_mesh* mesh, const float* x, float* y, void* stream);
 
 /* Moves between FP64 vectors ([E][G][N] doubles, device) and FP32 vectors in

@@ -587,7 +587,19 @@ int upload_cg_operands(stdg_mesh* m) {
         case 4: spd = cg_operands<4>(m, t, invs); break;
         case 10: spd = cg_operands<10>(m, t, invs); break;
         case 20: spd = cg_operands<20>(m, t, invs); break;
-        default: return STDG_OK;        // no fused kernel for this degree
+        default: {
+            // no tile kernel for this degree: the own-block inverses for the
+            // element-per-lane operator tables only
+            const int N = m->N;
+            invs.assign((size_t)m->n_classes * N * N, 0.0);
+            for (int c = 0; c < m->n_classes; ++c) {
+                const double* B0 = m->blocks.data() + (size_t)c * 5 * N * N;
+                std::vector<real> chol(B0, B0 + N * N), inv(B0, B0 + N * N);
+                if (!cholesky(N, chol) || !lu_inverse(N, inv)) { invs.assign(invs.size(), 0.0); break; }
+                for (int i = 0; i < N * N; ++i) invs[(size_t)c * N * N + i] = (double)inv[i];
+            }
+            return upload_lane_operands(m, invs);
+        }
     }
     m->d.cg_precond_ok = spd ? 1 : 0;
     STDG_HIP(hipMalloc(&m->d.aop32, t.size() * sizeof(float)));

@@ -1,8 +1,9 @@
-// Element-per-lane FP32 kernels of the inner pressure solve (eq. CS_19) on
-// meshes whose 64-element runs share one geometry class: the operator
-// y = c B x (B = dt^2 S^sp on one time node), the block-Jacobi step
-// y = s B_e^-1 x, and the one-kernel preconditioned CG iteration whose
-// recurrences are documented with k_cg_op (cg_fused.hip).
+// Element-per-lane FP32 kernels of the inner pressure solve (eq. CS_19): the
+// operator y = c B x (B = dt^2 S^sp on one time node) and the block-Jacobi
+// step y = s B_e^-1 x (p = 1, 2, 3, 4), and the one-kernel preconditioned CG
+// iteration whose recurrences are documented with k_cg_op in cg_fused.hip
+// (p = 1, 2, 3).  They serve meshes whose 64-element runs share one geometry
+// class (the operator also takes runs of several classes, one pass each).
 //
 // One wavefront per (64-element run, time node), lane l = element 64 run + l.
 // A lane holds whole rows of its element (the N values, loaded with the
@@ -37,6 +38,7 @@
 // such load over 64 rows of 4 N bytes.
 
 #include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "internal.hpp"
@@ -111,31 +113,27 @@ template <int N> __device__ inline void row_store(Rsrc r, uint32_t off, const fl
     }
 }
 
-// acc += A column held by quad q (broadcast to the 16 blocks) times b; q must
-// fold to a constant (every caller is fully unrolled)
-__device__ __forceinline__ f4 mfma_bcast(float a, float b, f4 acc, int q) {
-#define STDG_Q(k) \
-    case k: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, acc, 4, k, 0);
-    switch (q) {
-        STDG_Q(0) STDG_Q(1) STDG_Q(2) STDG_Q(3) STDG_Q(4) STDG_Q(5) STDG_Q(6) STDG_Q(7)
-        STDG_Q(8) STDG_Q(9) STDG_Q(10) STDG_Q(11) STDG_Q(12) STDG_Q(13) STDG_Q(14)
-        default: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, acc, 4, 15, 0);
-    }
-#undef STDG_Q
+// Step I of block BLK: contraction index c = I / NQ, row group rb = I % NQ,
+// operand t = (BLK NQ + rb) N + c held by quad t % 16 in register t / 16;
+// the A column of that quad is broadcast to the 16 blocks (cbsz 4, abid).
+template <int N, int BLK, int I>
+__device__ __forceinline__ void lane_step(const float (&ops)[LaneShape<N>::NV], const float (&b)[N],
+                                          f4 (&acc)[LaneShape<N>::NQ]) {
+    constexpr int NQ = LaneShape<N>::NQ, c = I / NQ, rb = I % NQ, t = (BLK * NQ + rb) * N + c;
+    acc[rb] = __builtin_amdgcn_mfma_f32_4x4x1f32(ops[t >> 4], b[c], acc[rb], 4, t & 15, 0);
+}
+
+template <int N, int BLK, int... I>
+__device__ __forceinline__ void lane_steps(const float (&ops)[LaneShape<N>::NV], const float (&b)[N],
+                                           f4 (&acc)[LaneShape<N>::NQ], std::integer_sequence<int, I...>) {
+    (lane_step<N, BLK, I>(ops, b, acc), ...);
 }
 
 // acc (rows 4 rb + i of the lane's element) += block BLK of the class times b
 template <int N, int BLK>
 __device__ __forceinline__ void lane_block(const float (&ops)[LaneShape<N>::NV], const float (&b)[N],
                                            f4 (&acc)[LaneShape<N>::NQ]) {
-    constexpr int NQ = LaneShape<N>::NQ;
-#pragma unroll
-    for (int c = 0; c < N; ++c)
-#pragma unroll
-        for (int rb = 0; rb < NQ; ++rb) {
-            const int t = (BLK * NQ + rb) * N + c;
-            acc[rb] = mfma_bcast(ops[t >> 4], b[c], acc[rb], t & 15);
-        }
+    lane_steps<N, BLK>(ops, b, acc, std::make_integer_sequence<int, N * LaneShape<N>::NQ>{});
 }
 
 template <int N> __device__ inline void acc_zero(f4 (&acc)[LaneShape<N>::NQ]) {
@@ -189,7 +187,12 @@ template <int N> __device__ inline void load_ops(const float* __restrict__ table
 }
 
 // ---------------------------------------------------------------- operator
-// y = cscale B x (cscale = c for p_gamma = 0, 1 for one time node of B (x) I)
+// A run whose lanes hold several classes (the class tails of a mesh with
+// boundary classes) takes one pass per class present: the class's operands,
+// then the products with the rows of the other classes' lanes read as zeros.
+// A run of one class takes a single pass.
+// y = cscale B x (cscale = c for p_gamma = 0, 1 for one time node of B (x) I);
+// the five rows of a pass are loaded one block ahead of their products
 template <int N>
 __global__ void __launch_bounds__(64 * LWPB) k_lane_op(const float* __restrict__ table, const int32_t* __restrict__ cls,
                                                        const int32_t* __restrict__ nbr, const float* x, float* y,
@@ -197,23 +200,35 @@ __global__ void __launch_bounds__(64 * LWPB) k_lane_op(const float* __restrict__
                                                        uint32_t vbytes) {
     const LanePos lp = lane_pos(E, G, n_waves);
     if (!lp.wact) return;
-    const int c = __builtin_amdgcn_readfirstlane(cls[lp.e0]);
+    const int mc = lp.valid ? cls[lp.e] : -1;
     const Rsrc rn = make_rsrc(nbr, 16u * (uint32_t)E);
     const i4v nb = __builtin_bit_cast(i4v, __builtin_amdgcn_raw_buffer_load_b128(rn, (int)(lp.valid ? 16u * lp.e : OOB), 0, 0));
     const int32_t rows[5] = {lp.e, nb.x, nb.y, nb.z, nb.w};
     const Rsrc rx = make_rsrc(x, vbytes);
-    float v[5][N];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) row_load<N>(rx, (lp.valid && rows[k] >= 0) ? run_off<N>(rows[k], lp.a, G) : OOB, v[k]);
-    float ops[LaneShape<N>::NV];
-    load_ops<N>(table, c, ops);
     f4 acc[LaneShape<N>::NQ];
     acc_zero<N>(acc);
-    lane_block<N, 0>(ops, v[0], acc);
-    lane_block<N, 1>(ops, v[1], acc);
-    lane_block<N, 2>(ops, v[2], acc);
-    lane_block<N, 3>(ops, v[3], acc);
-    lane_block<N, 4>(ops, v[4], acc);
+    float ops[LaneShape<N>::NV];
+    for (uint64_t todo = __ballot(lp.valid); todo;) {
+        const int c = __builtin_amdgcn_readlane(mc, __builtin_ctzll(todo));
+        const bool mine = lp.valid && mc == c;
+        todo &= ~__ballot(mine);
+        load_ops<N>(table, c, ops);
+        uint32_t off[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) off[k] = (mine && rows[k] >= 0) ? run_off<N>(rows[k], lp.a, G) : OOB;
+        float v[2][N];
+        row_load<N>(rx, off[0], v[0]);
+        auto blk = [&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            if constexpr (k < 4) row_load<N>(rx, off[k + 1], v[(k + 1) & 1]);
+            lane_block<N, k>(ops, v[k & 1], acc);
+        };
+        blk(std::integral_constant<int, 0>{});
+        blk(std::integral_constant<int, 1>{});
+        blk(std::integral_constant<int, 2>{});
+        blk(std::integral_constant<int, 3>{});
+        blk(std::integral_constant<int, 4>{});
+    }
     float o[N];
     acc_rows<N>(acc, cscale, o);
     // every lane of the run stores (the slots past the mesh get zeros)
@@ -228,15 +243,21 @@ __global__ void __launch_bounds__(64 * LWPB) k_lane_prec(const float* __restrict
                                                          uint32_t vbytes) {
     const LanePos lp = lane_pos(E, G, n_waves);
     if (!lp.wact) return;
-    const int c = __builtin_amdgcn_readfirstlane(cls[lp.e0]);
+    const int mc = lp.valid ? cls[lp.e] : -1;
     const uint32_t off0 = run_off<N>(lp.e, lp.a, G);
-    float v[N];
-    row_load<N>(make_rsrc(x, vbytes), lp.valid ? off0 : OOB, v);
-    float ops[LaneShape<N>::NV];
-    load_ops<N>(table, c, ops);
+    const Rsrc rx = make_rsrc(x, vbytes);
     f4 acc[LaneShape<N>::NQ];
     acc_zero<N>(acc);
-    lane_block<N, 5>(ops, v, acc);
+    float ops[LaneShape<N>::NV];
+    for (uint64_t todo = __ballot(lp.valid); todo;) {
+        const int c = __builtin_amdgcn_readlane(mc, __builtin_ctzll(todo));
+        const bool mine = lp.valid && mc == c;
+        todo &= ~__ballot(mine);
+        load_ops<N>(table, c, ops);
+        float v[N];
+        row_load<N>(rx, mine ? off0 : OOB, v);
+        lane_block<N, 5>(ops, v, acc);
+    }
     float o[N];
     acc_rows<N>(acc, scale, o);
     row_store<N>(make_rsrc(y, vbytes), off0, o);
@@ -649,20 +670,33 @@ bool lane_supported(const stdg_mesh* m) { return m->d.lane_ops != nullptr; }
 // of the mesh holds one class.  inv: [n_classes][N][N] inverse own blocks
 // (zeros where the block is not SPD).
 int upload_lane_operands(stdg_mesh* m, const std::vector<double>& inv) {
-    if (m->N != 4 && m->N != 10 && m->N != 20) return STDG_OK;
-    for (int64_t t0 = 0; t0 < m->E; t0 += 64)
-        for (int64_t e = t0 + 1; e < std::min<int64_t>(t0 + 64, m->E); ++e)
-            if (m->cls[e] != m->cls[t0]) return STDG_OK;
+    if (m->N != 4 && m->N != 10 && m->N != 20 && m->N != 35) return STDG_OK;
+    // class passes of the runs (one per distinct class in a run)
+    int64_t runs = 0, passes = 0;
+    for (int64_t t0 = 0; t0 < m->E; t0 += 64, ++runs) {
+        std::vector<int32_t> seen;
+        for (int64_t e = t0; e < std::min<int64_t>(t0 + 64, m->E); ++e)
+            if (std::find(seen.begin(), seen.end(), m->cls[e]) == seen.end()) seen.push_back(m->cls[e]);
+        passes += (int64_t)seen.size();
+    }
+    // p = 1, 2, 3 keep the element-major tile kernels unless every run has
+    // one class; p = 4 (no tile kernel) takes the element-per-lane operator
+    // while the extra passes stay few
+    if (m->N != 35 ? passes != runs : 2 * passes > 3 * runs) return STDG_OK;
     std::vector<float> t;
     switch (m->N) {
         case 4: lane_table<4>(m, inv, t); break;
         case 10: lane_table<10>(m, inv, t); break;
-        default: lane_table<20>(m, inv, t); break;
+        case 20: lane_table<20>(m, inv, t); break;
+        default: lane_table<35>(m, inv, t); break;
     }
     STDG_HIP(hipMalloc(&m->d.lane_ops, t.size() * sizeof(float)));
     STDG_HIP(hipMemcpy(m->d.lane_ops, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
-    return upload_chunk_tables(m);
+    return m->N == 35 ? STDG_OK : upload_chunk_tables(m);
 }
+
+// the one-kernel CG iteration runs in the run layout (p = 1, 2, 3)
+bool lane_iter_supported(const stdg_mesh* m) { return m->d.lane_ops != nullptr && m->N != 35; }
 
 // workgroups of the per-run kernels (a multiple of the 8 XCDs)
 int64_t lane_run_blocks(const stdg_mesh* m) { return ((int64_t)lane_waves(m) + LWPB - 1) / LWPB / 8 * 8 + 8; }
@@ -714,7 +748,7 @@ hipError_t lane_apply_f32(const stdg_mesh* m, const float* x, float* y, float cs
                            (int32_t)m->E, (int32_t)m->G, lane_waves(m), vbytes);                                   \
         return hipGetLastError();
     switch (m->N) {
-        STDG_N(4) STDG_N(10) STDG_N(20)
+        STDG_N(4) STDG_N(10) STDG_N(20) STDG_N(35)
         default: return hipErrorInvalidValue;
     }
 #undef STDG_N
@@ -729,7 +763,7 @@ hipError_t lane_prec_f32(const stdg_mesh* m, const float* x, float* y, float sca
                            (int32_t)m->G, lane_waves(m), vbytes);                                                  \
         return hipGetLastError();
     switch (m->N) {
-        STDG_N(4) STDG_N(10) STDG_N(20)
+        STDG_N(4) STDG_N(10) STDG_N(20) STDG_N(35)
         default: return hipErrorInvalidValue;
     }
 #undef STDG_N

@@ -1255,8 +1255,16 @@ extern "C" int stdg_pressure_apply_spatial_f32(const stdg_mesh* cm, const float*
     if (!cm || !x || !y) { set_error("null argument"); return STDG_ERR_ARG; }
     stdg_mesh* m = const_cast<stdg_mesh*>(cm);
     if (!m->d.blocks) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
-    if (!cg_fused_supported(m)) { set_error("the FP32 spatial operator kernel supports p = 1, 2, 3"); return STDG_ERR_ARG; }
-    const hipError_t e = launch_cg_apply_f32(m, x, y, 1.0f, (hipStream_t)stream);
+    hipError_t e;
+    if (lane_supported(m)) {
+        e = lane_apply_f32(m, x, y, 1.0f, (hipStream_t)stream);
+    } else if (cg_fused_supported(m)) {
+        e = launch_cg_apply_f32(m, x, y, 1.0f, (hipStream_t)stream);
+    } else {
+        set_error("no FP32 MFMA spatial operator for this mesh (p = 1, 2, 3, or p = 4 on meshes whose "
+                  "64-element runs mostly share a geometry class)");
+        return STDG_ERR_ARG;
+    }
     if (e != hipSuccess) { set_error(std::string("spatial apply: ") + hipGetErrorString(e)); return STDG_ERR_DEVICE; }
     return STDG_OK;
 }

@@ -235,3 +235,6 @@ def test_learned_guess_keeps_solution_and_saves_iterations():
     print({k: sum(v) for k, v in its.items()}, {k: sum(v) for k, v in steps_its.items()}, flush=True)
     assert sum(its[P.STDG_KRYLOV_LEARNED]) < sum(its[P.STDG_KRYLOV_PREVIOUS])
     assert sum(its[P.STDG_KRYLOV_LEARNED]) < sum(its[P.STDG_KRYLOV_ZERO])
+    # the network's own contribution: the learned start is the extrapolation
+    # plus the fitted network term, so it must beat the extrapolation alone
+    assert sum(its[P.STDG_KRYLOV_LEARNED]) < sum(its[P.STDG_KRYLOV_EXTRAPOLATE])

@@ -179,19 +179,22 @@ def test_inner_layout_moves(n, p, pg, periodic):
     assert np.array_equal(back.cpu().numpy(), x.ravel())
 
 
-@pytest.mark.parametrize("n,p,pg", [(8, 3, 1), (48, 3, 0), (32, 2, 1), (24, 3, 1)])
-def test_spatial_apply_f32_sampled_rows(n, p, pg):
-    """The FP32 spatial operator (B (x) I) of the time-decoupled inner solve on
-    periodic cubes whose 64-element runs share a class, so the element-per-lane
-    kernel runs in the run layout (the 663,552-, 196,608- and 82,944-element
-    cubes at full size): sampled rows against the oracle's S (I (x) C^-1) x,
-    1e-5 relative."""
-    print(f"spatial f32 sampled n={n} p={p} pg={pg}", flush=True)
+@pytest.mark.parametrize("n,p,pg,periodic", [(8, 3, 1, True), (48, 3, 0, True), (32, 2, 1, True),
+                                             (24, 3, 1, True), (4, 4, 0, True), (4, 4, 1, True),
+                                             (8, 4, 1, False)])
+def test_spatial_apply_f32_sampled_rows(n, p, pg, periodic):
+    """The FP32 spatial operator (B (x) I) of the time-decoupled inner solve
+    in the run layout of the element-per-lane kernel: periodic cubes whose
+    64-element runs share a class (the 663,552-, 196,608- and 82,944-element
+    cubes at full size) and, at p = 4, the 8^3 Dirichlet cube whose class
+    tails mix classes within a run (one pass per class): sampled rows against
+    the oracle's S (I (x) C^-1) x, 1e-5 relative."""
+    print(f"spatial f32 sampled n={n} p={p} pg={pg} periodic={periodic}", flush=True)
     dt = 1e-3
     X, T = kuhn_mesh(n)
-    m = P.Mesh(X, T, p, pg, dt=dt, periodic=True)
+    m = P.Mesh(X, T, p, pg, dt=dt, periodic=periodic)
     assert m.inner_layout == P.STDG_LAYOUT_RUN
-    ops = SpaceTimeOperators(OracleMesh(X, T, periodic=True), p, pg, dt)
+    ops = SpaceTimeOperators(OracleMesh(X, T, periodic=periodic), p, pg, dt)
     rng = np.random.default_rng(40 + n)
     x = rng.standard_normal((m.E, m.G, m.N)).astype(np.float32).astype(np.float64)
     xs = np.einsum("ab,ebn->ean", _time_factor_inverse(pg), x).reshape(m.E, m.Nst)
@@ -275,8 +278,9 @@ SOLVE = [  # n, p, pg, periodic, jitter, method, precision
     (3, 2, 1, True, 0.0, P.STDG_BICGSTAB, P.STDG_FP32),
     (3, 2, 1, True, 0.1, P.STDG_CG_TIME, P.STDG_FP32),   # fused FP32 PCG, every tile mixing classes
     (3, 3, 0, True, 0.1, P.STDG_CG, P.STDG_FP32),
-    (8, 2, 0, True, 0.0, P.STDG_CG, P.STDG_FP32),     # cycle-staged FP32 PCG, 8 chunks with halos
+    (8, 2, 0, True, 0.0, P.STDG_CG, P.STDG_FP32),     # chunk-staged FP32 PCG, 8 chunks with halos
     (8, 3, 0, True, 0.0, P.STDG_CG, P.STDG_FP32),     # the same at the headline degree (N = 20)
+    (2, 4, 1, False, 0.0, P.STDG_CG_TIME, P.STDG_FP32),   # p = 4: FP32 refinement, element-major layout
 ]
 
 
@@ -301,6 +305,35 @@ def test_solve_matches_oracle(n, p, pg, periodic, jitter, method, precision):
     assert rep.rel_residual <= 1e-12
     xs = to_input(xg.cpu().numpy().reshape(m.E, m.Nst), perm)
     assert np.abs(xs - xo).max() <= 1e-8 * np.abs(xo).max()
+
+
+@pytest.mark.parametrize("n,pg,periodic", [(4, 1, True), (8, 2, False)])
+def test_fp32_refinement_p4_run_layout(n, pg, periodic):
+    """p = 4 (N = 35): the FP32 inner CG of the time-decoupled solve runs the
+    element-per-lane MFMA operator in the run layout (the 8^3 Dirichlet cube
+    with one pass per class in its mixed runs); the refined pressure matches
+    the FP64 CG solve of the same system to 1e-8 relative, both solved to a
+    1e-12 residual (two solves that each meet 1e-10 may differ by the
+    condition number times 1e-10: 2.8e-7 on the Dirichlet cube)."""
+    X, T = kuhn_mesh(n)
+    m = P.Mesh(X, T, 4, pg, dt=1e-2, periodic=periodic)
+    assert m.inner_layout == P.STDG_LAYOUT_RUN
+    rng = np.random.default_rng(17)
+    xt = gpu(rng.standard_normal(m.E * m.Nst))
+    b = torch.empty_like(xt)
+    m.apply(xt, b)
+    x32 = torch.zeros_like(b)
+    r32 = m.solve(b, x32, method=P.STDG_CG_TIME, precision=P.STDG_FP32, rtol=1e-12, inner_rtol=1e-5,
+                  max_iter=200000)
+    x64 = torch.zeros_like(b)
+    r64 = m.solve(b, x64, method=P.STDG_CG_TIME, precision=P.STDG_FP64, rtol=1e-12, max_iter=200000)
+    torch.cuda.synchronize()
+    err = float((x32 - x64).abs().max() / x64.abs().max())
+    print(f"p=4 n={n} pg={pg}: FP32 {r32.inner_iters} it / {r32.outer_iters} refinements, FP64 {r64.inner_iters} it, "
+          f"difference {err:.2e}", flush=True)
+    assert r32.status == P.STDG_OK and r64.status == P.STDG_OK
+    assert r32.rel_residual <= 1e-12
+    assert err <= 1e-8
 
 
 def test_solve_reports_not_converged_and_nan():
