@@ -210,6 +210,112 @@ __global__ void __launch_bounds__(256) schur_apply_rows(
     }
 }
 
+// Element-per-lane FP64 apply for meshes whose 64-element runs share a class
+// (the structured cubes).  One wavefront (and workgroup) per run, lane l =
+// element 64 run + l; for each of the five couplings the wavefront first
+// moves the 64 rows it needs ([G][N] doubles each, contiguous in memory)
+// into its LDS with 16-byte loads that walk the rows in order (a load
+// instruction covers about 64 / (N G / 2) consecutive rows instead of one
+// row per lane), then every lane reads its own row back and applies the
+// class block, taken column by column through scalar loads (uniform on the
+// run), to all G time nodes of its element.  The G x G time factor is
+// applied to the result, which leaves through LDS the same way.  Row pieces
+// sit in LDS at an odd stride of 16-byte units (NP + 1 for even NP), so the
+// 16 lanes of each pass of a 16-byte read hit distinct banks.
+template <int N, int G>
+__global__ void __launch_bounds__(64) schur_apply_run(const double* __restrict__ BT, const int32_t* __restrict__ cls,
+                                                      const int32_t* __restrict__ nbr, const double* __restrict__ C,
+                                                      const double* __restrict__ x, double* __restrict__ y,
+                                                      int64_t E, uint32_t n_runs) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    constexpr int R = N * G, NP = R / 2, STR = NP % 2 == 0 ? NP + 1 : NP;
+    static_assert(R % 2 == 0, "rows of whole 16-byte pieces");
+    __shared__ d2 L[64 * STR];
+    const int lane = threadIdx.x;
+    // consecutive workgroups go round-robin to the 8 XCDs: XCD x takes the
+    // contiguous range of runs x * per ..
+    const uint32_t nb = gridDim.x;
+    const uint32_t run = (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
+    if (run >= n_runs) return;
+    const int64_t e0 = (int64_t)run * 64, e = e0 + lane;
+    const bool valid = e < E;
+    const int c = __builtin_amdgcn_readfirstlane(cls[e0]);
+    int nbk[4] = {-1, -1, -1, -1};
+    if (valid) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) nbk[f] = nbr[4 * e + f];
+    }
+    double z[G][N];
+#pragma unroll
+    for (int b = 0; b < G; ++b)
+#pragma unroll
+        for (int r = 0; r < N; ++r) z[b][r] = 0.0;
+    for (int k = 0; k < 5; ++k) {
+        const int src = k == 0 ? (valid ? (int)e : -1) : nbk[k - 1];
+        if (__builtin_amdgcn_readfirstlane(__ballot(src >= 0) != 0 ? 1 : 0) == 0) continue;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int pc = i * 64 + lane, row = pc / NP, piece = pc - row * NP;
+            const int s = __shfl(src, row, 64);
+            const d2 v = s >= 0 ? reinterpret_cast<const d2*>(x + (int64_t)s * R)[piece] : d2{0.0, 0.0};
+            L[row * STR + piece] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double xr[R];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const d2 t = L[lane * STR + j];
+            xr[2 * j] = t.x;
+            xr[2 * j + 1] = t.y;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double* Bk = BT + ((int64_t)c * 5 + k) * N * N;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            const double* col = Bk + m * N;
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                const double a = col[r];
+#pragma unroll
+                for (int b = 0; b < G; ++b) z[b][r] += a * xr[b * N + m];
+            }
+        }
+    }
+    double yr[R];
+#pragma unroll
+    for (int a = 0; a < G; ++a)
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < G; ++b) s += C[a * G + b] * z[b][r];
+            yr[a * N + r] = s;
+        }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) L[lane * STR + j] = d2{yr[2 * j], yr[2 * j + 1]};
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const int pc = i * 64 + lane, row = pc / NP, piece = pc - row * NP;
+        if (e0 + row < E) reinterpret_cast<d2*>(y + (e0 + row) * R)[piece] = L[row * STR + piece];
+    }
+}
+
+template <int N, int G>
+static hipError_t launch_run(const stdg_mesh* m, const double* C, const double* x, double* y, hipStream_t s) {
+    const uint32_t runs = (uint32_t)((m->E + 63) / 64);
+    const uint32_t blocks = (runs + 7) / 8 * 8;
+    hipLaunchKernelGGL((schur_apply_run<N, G>), dim3(blocks), dim3(64), 0, s, m->d.blocks, m->d.cls, m->d.nbr, C,
+                       x, y, m->E, runs);
+    return hipGetLastError();
+}
+
 template <int N, int G, typename T>
 static hipError_t launch_tn(const stdg_mesh* m, const T* BT, const T* C, const T* x, T* y, hipStream_t s) {
     const int64_t blocks = (m->E + 255) / 256 * G;
@@ -253,6 +359,17 @@ static hipError_t launch_apply(const stdg_mesh* m, const T* BT, const T* C, cons
     // nodes with N >= 20 (N=20,G=2: 92 vs 116 us; N=35,G=5: 364 vs 464 us on
     // the 82,944 / 24,576-element meshes), the direct-gather kernel elsewhere
     // and for FP32 everywhere.
+    if constexpr (sizeof(T) == 8) {
+        if (m->d.runs_uniform && m->E < (int64_t(1) << 31)) {
+#define STDG_NG(n, g) \
+    if (m->N == n && m->G == g) return launch_run<n, g>(m, C, x, y, s);
+            // measured on MI355X: 196,608-element p = 2, p_gamma = 1 cube 54 -> 32 us; at N = 20 the
+            // scalar operand stream (one FMA per scalar value and lane) makes it slower than the
+            // kernels below (663,552 elements, G = 1: 186 vs 170 us; 82,944, G = 2: 137 vs 92 us)
+            STDG_NG(4, 1) STDG_NG(4, 2) STDG_NG(10, 1) STDG_NG(10, 2)
+#undef STDG_NG
+        }
+    }
     if (sizeof(T) == 8 && m->G >= 2) {
 #define STDG_NG(n, g) \
     if (m->N == n && m->G == g) return launch_lds<n, g, T>(m, BT, C, x, y, s);

@@ -4,6 +4,8 @@
 #include <new>
 #include <string>
 
+#include <algorithm>
+
 #include "internal.hpp"
 #include "kernels.hpp"
 
@@ -30,6 +32,10 @@ int upload_tables(stdg_mesh* m) {
             }
     std::vector<float> c32(m->Ctime.begin(), m->Ctime.end());
     std::vector<int32_t> cls(m->cls.begin(), m->cls.end());
+    m->d.runs_uniform = 1;
+    for (int64_t t0 = 0; t0 < m->E && m->d.runs_uniform; t0 += 64)
+        for (int64_t e = t0 + 1; e < std::min<int64_t>(t0 + 64, m->E); ++e)
+            if (cls[e] != cls[t0]) { m->d.runs_uniform = 0; break; }
     STDG_HIP(hipMalloc(&m->d.blocks, nb * sizeof(double)));
     STDG_HIP(hipMalloc(&m->d.blocks32, nb * sizeof(float)));
     STDG_HIP(hipMalloc(&m->d.cls, m->E * sizeof(int32_t)));

@@ -42,6 +42,7 @@ struct DeviceTables {
     int chunk_hmax = 0;             // halo rows per chunk (multiple of 64)
     int64_t chunk_chunks = 0;
     float* lane_ops = nullptr;    // class operands of the element-per-lane kernels (null: a run mixes classes)
+    int runs_uniform = 0;         // every 64-element run of the element order holds one class
     int32_t* cls = nullptr;       // [E]
     int32_t* nbr = nullptr;       // [E][4]  -1 on a boundary face
     double* C = nullptr;          // [G][G]  time factor W T^-1 W

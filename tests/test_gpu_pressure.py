@@ -41,7 +41,10 @@ def lib_apply(m, x_int, precision=P.STDG_FP64):
 SMALL = [  # n, p, p_gamma, periodic, jitter
     (2, 1, 0, False, 0.0), (2, 2, 0, False, 0.15), (3, 2, 1, True, 0.0),
     (3, 3, 0, False, 0.0), (2, 2, 2, False, 0.1), (3, 1, 3, True, 0.0),
-    (2, 4, 1, False, 0.0), (2, 5, 0, False, 0.0)]
+    (2, 4, 1, False, 0.0), (2, 5, 0, False, 0.0),
+    # periodic 4^3 cube: every 64-element run holds one class, so the FP64
+    # apply runs the element-per-lane kernel (p = 1, 2)
+    (4, 1, 1, True, 0.0), (4, 2, 0, True, 0.0), (4, 2, 1, True, 0.0), (4, 3, 1, True, 0.0)]
 
 
 @pytest.mark.parametrize("n,p,pg,periodic,jitter", SMALL)
