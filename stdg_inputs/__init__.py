@@ -15,6 +15,8 @@ Layout conventions (they define the meaning of every coefficient vector):
 * Time nodes are the Gauss-Legendre points of [0, 1] (Sec. 2.3); the time
   coefficient with index a is the value at the a-th point in ascending order.
 * Pressure vectors are laid out [tet][time node][spatial node].
+* A curved element is given by the physical positions of its spatial nodes,
+  in the same order ([tet][node][3]).
 """
 
 from .mesh import kuhn_mesh, hex_count_for
@@ -22,8 +24,9 @@ from .fields import (beltrami_velocity, beltrami_pressure, fourier_modes,
                      fourier_velocity)
 from .nodes import (node_reference_points, node_coordinates, time_nodes,
                     n_spatial)
+from .curved import curved_mesh, deform
 
 __all__ = ["kuhn_mesh", "hex_count_for", "beltrami_velocity",
            "beltrami_pressure", "fourier_modes", "fourier_velocity",
            "node_reference_points", "node_coordinates", "time_nodes",
-           "n_spatial"]
+           "n_spatial", "curved_mesh", "deform"]
