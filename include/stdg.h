@@ -129,6 +129,31 @@ int stdg_mesh_build(const double* xyz, int64_t n_vert, const int64_t* tets,
 int stdg_mesh_build_host(const double* xyz, int64_t n_vert, const int64_t* tets,
                          int64_t n_tet, const stdg_config* cfg, stdg_mesh** out);
 
+/* Mesh with curved (isoparametric) elements, Sec. 2.8.  As stdg_mesh_build
+ * (host_only != 0: as stdg_mesh_build_host), plus nodes[n_tet][N][3] (HOST):
+ * the physical positions of each element's N spatial nodes, in the layout
+ * order of the pressure coefficients (reference points (j1, j2, j3)/p, j1
+ * fastest, in the element's local vertex frame).  Element i is the image of
+ * the reference tetrahedron under x_i(xi) = sum_k nodes[i][k] phi_k(xi);
+ * the sub-tetrahedra of its dual elements are the images of the reference
+ * sub-tetrahedra (reference face and barycentre), and a face is met by its
+ * two elements at equal barycentric coordinates of its vertices, so the
+ * nodes on a shared face must coincide (translated on periodic faces).
+ * Every integral is exact (reference coordinates, polynomial integrands of
+ * degree <= 2p^2 + 3p - 3), so the precompute costs O(p^8) per curved element;
+ * elements whose nodes are the affine image of the reference nodes, and
+ * whose neighbours' are too, keep the straight precompute and share blocks.
+ * Only the pressure system is built on a curved mesh: stdg_pressure_apply,
+ * stdg_pressure_solve and the model calls accept it; stdg_picard_step,
+ * stdg_dual_from_main, stdg_main_from_dual and stdg_divergence return
+ * STDG_ERR_ARG.  When no element is curved the mesh is the straight one.
+ * Errors: those of stdg_mesh_build; STDG_ERR_ARG for nodes == NULL;
+ * STDG_ERR_MESH when vertex nodes differ from xyz (relative 1e-12) or two
+ * elements do not share a curved face (relative 1e-9). */
+int stdg_mesh_build_curved(const double* xyz, int64_t n_vert, const int64_t* tets,
+                           int64_t n_tet, const double* nodes, int32_t host_only,
+                           const stdg_config* cfg, stdg_mesh** out);
+
 /* Copy the precomputed pressure-operator tables to host arrays:
  * blocks[n_classes][5][N][N] (dt^2-scaled spatial blocks; block 0 multiplies
  * the element itself, block 1+f the neighbour across local face f),

@@ -75,7 +75,9 @@ class Mesh:
 
     def __init__(self, X, tets, p, p_gamma=0, dt=1e-2, nu=0.0, periodic=False,
                  box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0), anchor_tet=0,
-                 anchor_node=0, reorder=True, device=True):
+                 anchor_node=0, reorder=True, device=True, nodes=None):
+        """nodes: optional (E, N, 3) positions of each element's spatial nodes
+        (curved isoparametric elements; only the pressure system is built)."""
         lib = _lib.load()
         X = np.ascontiguousarray(X, dtype=np.float64)
         tets = np.ascontiguousarray(tets, dtype=np.int64)
@@ -87,9 +89,18 @@ class Mesh:
         cfg.anchor_tet, cfg.anchor_node = anchor_tet, anchor_node
         cfg.reorder = 1 if reorder else 0
         h = ctypes.c_void_p()
-        fn = lib.stdg_mesh_build if device else lib.stdg_mesh_build_host
-        _lib.check(fn(X.ctypes.data, X.shape[0], tets.ctypes.data, tets.shape[0],
-                      ctypes.byref(cfg), ctypes.byref(h)))
+        if nodes is not None:
+            nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+            N = (p + 1) * (p + 2) * (p + 3) // 6
+            if nodes.shape != (tets.shape[0], N, 3):
+                raise ValueError(f"nodes must have shape ({tets.shape[0]}, {N}, 3)")
+            _lib.check(lib.stdg_mesh_build_curved(X.ctypes.data, X.shape[0], tets.ctypes.data, tets.shape[0],
+                                                  nodes.ctypes.data, 0 if device else 1,
+                                                  ctypes.byref(cfg), ctypes.byref(h)))
+        else:
+            fn = lib.stdg_mesh_build if device else lib.stdg_mesh_build_host
+            _lib.check(fn(X.ctypes.data, X.shape[0], tets.ctypes.data, tets.shape[0],
+                          ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
         self._lib = lib
         self.device = device

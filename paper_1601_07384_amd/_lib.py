@@ -113,6 +113,8 @@ SIGNATURES = [
                                         ctypes.POINTER(Config), ctypes.POINTER(_P)]),
     ("stdg_mesh_build_host", ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.c_int64,
                                              ctypes.POINTER(Config), ctypes.POINTER(_P)]),
+    ("stdg_mesh_build_curved", ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.c_int64, _P, ctypes.c_int32,
+                                               ctypes.POINTER(Config), ctypes.POINTER(_P)]),
     ("stdg_mesh_blocks", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("stdg_mesh_info_get", ctypes.c_int, [_P, ctypes.POINTER(MeshInfo)]),
     ("stdg_mesh_permutation", ctypes.c_int, [_P, _P]),

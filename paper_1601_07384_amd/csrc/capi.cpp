@@ -84,7 +84,7 @@ using namespace stdg;
 extern "C" const char* stdg_last_error(void) { return g_last_error.c_str(); }
 
 static int mesh_build_impl(const double* xyz, int64_t n_vert, const int64_t* tets, int64_t n_tet,
-                           const stdg_config* cfg, stdg_mesh** out, bool device) {
+                           const double* nodes, const stdg_config* cfg, stdg_mesh** out, bool device) {
     if (!xyz || !tets || !cfg || !out) { set_error("null argument"); return STDG_ERR_ARG; }
     *out = nullptr;
     if (n_vert < 4 || n_tet < 1 || n_tet > (int64_t)INT32_MAX) { set_error("bad mesh size"); return STDG_ERR_ARG; }
@@ -110,20 +110,24 @@ static int mesh_build_impl(const double* xyz, int64_t n_vert, const int64_t* tet
         m->E = n_tet;
         std::vector<int64_t> rep;
         int e = build_topology(m, xyz, n_vert, tets, nullptr);
+        if (e == STDG_OK && nodes) e = set_geometry(m, nodes);
         if (e == STDG_OK) e = assign_classes(m, rep);
         if (e == STDG_OK && cfg->reorder) {
             const std::vector<int64_t> order = class_chunk_order(m);
             e = build_topology(m, xyz, n_vert, tets, &order);
+            if (e == STDG_OK && nodes) e = set_geometry(m, nodes);
             if (e == STDG_OK) e = assign_classes(m, rep);
         }
         if (e == STDG_OK) sort_faces_by_class(m);
         if (e == STDG_OK) e = build_blocks(m, rep);
-        if (e == STDG_OK) e = build_picard_tables(m, rep);
+        // curved elements: the pressure system only (the Picard-step tables
+        // assume affine elements)
+        if (e == STDG_OK && !m->curved) e = build_picard_tables(m, rep);
         if (e == STDG_OK) {
             m->anchor = m->iperm[cfg->anchor_tet];
             m->anchor_node = cfg->anchor_node;
             if (device) e = upload_tables(m);
-            if (device && e == STDG_OK) e = upload_picard_tables(m);
+            if (device && e == STDG_OK && !m->curved) e = upload_picard_tables(m);
         }
         if (e != STDG_OK) {
             free_picard(m);
@@ -146,12 +150,19 @@ static int mesh_build_impl(const double* xyz, int64_t n_vert, const int64_t* tet
 
 extern "C" int stdg_mesh_build(const double* xyz, int64_t n_vert, const int64_t* tets, int64_t n_tet,
                                const stdg_config* cfg, stdg_mesh** out) {
-    return mesh_build_impl(xyz, n_vert, tets, n_tet, cfg, out, true);
+    return mesh_build_impl(xyz, n_vert, tets, n_tet, nullptr, cfg, out, true);
 }
 
 extern "C" int stdg_mesh_build_host(const double* xyz, int64_t n_vert, const int64_t* tets, int64_t n_tet,
                                     const stdg_config* cfg, stdg_mesh** out) {
-    return mesh_build_impl(xyz, n_vert, tets, n_tet, cfg, out, false);
+    return mesh_build_impl(xyz, n_vert, tets, n_tet, nullptr, cfg, out, false);
+}
+
+extern "C" int stdg_mesh_build_curved(const double* xyz, int64_t n_vert, const int64_t* tets, int64_t n_tet,
+                                      const double* nodes, int32_t host_only, const stdg_config* cfg,
+                                      stdg_mesh** out) {
+    if (!nodes) { set_error("null argument"); return STDG_ERR_ARG; }
+    return mesh_build_impl(xyz, n_vert, tets, n_tet, nodes, cfg, out, host_only == 0);
 }
 
 extern "C" int stdg_mesh_blocks(const stdg_mesh* m, double* blocks, int32_t* cls, int32_t* nbr, double* C) {

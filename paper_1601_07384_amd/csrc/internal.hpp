@@ -73,6 +73,7 @@ struct Workspace {
 };
 
 V3 centroid(const std::array<V3, 4>& v);
+int set_geometry(stdg_mesh* m, const double* nodes);        // curved elements (Sec. 2.8)
 V3 neighbour_shift(const stdg_mesh* m, int64_t t, int f);   // brings the neighbour next to t
 void taylor_eval(const std::vector<std::array<int, 3>>& ex, const V3& x, const V3& x0, real h, real* out);
 
@@ -114,6 +115,9 @@ struct stdg_mesh {
     std::vector<int64_t> perm;        // internal -> input
     std::vector<int64_t> iperm;       // input -> internal
     std::vector<std::array<stdg::V3, 4>> vert;   // internal order, local vertex order kept
+    std::vector<stdg::V3> geo;        // [E][N] isoparametric nodes (curved meshes), internal order
+    std::vector<uint8_t> bent;        // [E] 1: the element's nodes are not an affine image
+    bool curved = false;              // some element is bent (Picard tables are not built)
     std::vector<int32_t> nbr;         // [E][4]
     std::vector<int64_t> tet_face;    // [E][4] face id
     std::vector<stdg::Face> faces;    // interior first, then boundary

@@ -162,6 +162,154 @@ static void dual_face_blocks(const NodalBasis& phi, int p, const std::array<V3, 
     }
 }
 
+// ---- curved (isoparametric) elements, Sec. 2.8 -------------------------
+// Element i is the image of the reference tetrahedron under
+// x_i(xi) = sum_k X_ik phi_k(xi) (the degree-p nodal basis through its N
+// nodes).  The sub-tetrahedron T_ij is the image under x_i of the reference
+// sub-tetrahedron spanned by the reference face and the reference
+// barycentre; the face is the image of the reference face, met by both
+// elements at equal barycentric coordinates of its three vertices.  All
+// integrals run in reference coordinates (dx = |det J| dxi, grad_x =
+// J^-T grad_xi, n dS = t_u x t_v du dv); the integrands are then
+// polynomials in xi of degree at most 2p^2 + 3(p-1) (volume) and
+// p^2 + 3p - 2 (face), which the collapsed rules below integrate exactly.
+
+static const V3 kRefVert[4] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+
+// Position and Jacobian (J[r*3+c] = dx_r/dxi_c) of the isoparametric map
+// with nodes X at xi; val (N) and grad (N x 3) receive the nodal basis there.
+static void iso_point(const NodalBasis& phi, const V3* X, const V3& xi, real* val, real* grad, V3& x,
+                      real J[9]) {
+    phi.eval(xi, val);
+    phi.grad(xi, grad);
+    x = {0, 0, 0};
+    for (int i = 0; i < 9; ++i) J[i] = 0;
+    for (int k = 0; k < phi.N; ++k)
+        for (int r = 0; r < 3; ++r) {
+            x[r] += X[k][r] * val[k];
+            for (int c = 0; c < 3; ++c) J[r * 3 + c] += X[k][r] * grad[3 * k + c];
+        }
+}
+
+static real inv3(const real J[9], real Ji[9]) {
+    const real det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                     J[2] * (J[3] * J[7] - J[4] * J[6]);
+    Ji[0] = (J[4] * J[8] - J[5] * J[7]) / det;
+    Ji[1] = (J[2] * J[7] - J[1] * J[8]) / det;
+    Ji[2] = (J[1] * J[5] - J[2] * J[4]) / det;
+    Ji[3] = (J[5] * J[6] - J[3] * J[8]) / det;
+    Ji[4] = (J[0] * J[8] - J[2] * J[6]) / det;
+    Ji[5] = (J[2] * J[3] - J[0] * J[5]) / det;
+    Ji[6] = (J[3] * J[7] - J[4] * J[6]) / det;
+    Ji[7] = (J[1] * J[6] - J[0] * J[7]) / det;
+    Ji[8] = (J[0] * J[4] - J[1] * J[3]) / det;
+    return det;
+}
+
+// Curved counterpart of dual_face_blocks: Xt, Xk the N nodes of element t
+// and of its neighbour across t's local face f (Xk translated by shk next to
+// t); kv[i] the neighbour's local vertex at t's i-th face vertex (face
+// vertices = t's local vertices other than f, ascending).  Returns -2 when the
+// two elements do not share the curved face.
+static int curved_face_blocks(const NodalBasis& phi, int p, const V3* Xt, int f, const V3* Xk, const V3& shk,
+                              const int kv[3], DualFaceBlocks& out) {
+    const int N = phi.N;
+    const auto ex = exponents(p);
+    const V3 bref = {0.25L, 0.25L, 0.25L};
+    int lv[3];
+    for (int k = 0, n = 0; k < 4; ++k)
+        if (k != f) lv[n++] = k;
+    V3 ref[2][3];
+    for (int i = 0; i < 3; ++i) {
+        ref[0][i] = kRefVert[lv[i]];
+        ref[1][i] = kRefVert[kv[i]];
+    }
+    const V3* X[2] = {Xt, Xk};
+    const V3 sh[2] = {{0, 0, 0}, shk};
+    std::vector<real> val(N), grad(3 * N), ps(N), gx(3 * N), ph[2] = {std::vector<real>(N), std::vector<real>(N)};
+    real J[9], Ji[9];
+    auto map = [&](int s, const V3& xi, V3& x) {
+        iso_point(phi, X[s], xi, val.data(), grad.data(), x, J);
+        x = add(x, sh[s]);
+    };
+    // dual basis centre and scale as on straight faces, with the element
+    // barycentres replaced by their images
+    V3 P[3], bc[2];
+    for (int i = 0; i < 3; ++i) map(0, ref[0][i], P[i]);
+    for (int s = 0; s < 2; ++s) map(s, bref, bc[s]);
+    real vol[2];
+    V3 cen[2];
+    for (int s = 0; s < 2; ++s) {
+        vol[s] = std::fabs(det3(sub(P[0], bc[s]), sub(P[1], bc[s]), sub(P[2], bc[s]))) / 6.0;
+        cen[s] = scale(add(add(P[0], P[1]), add(P[2], bc[s])), 0.25);
+    }
+    const V3 x0 = scale(add(scale(cen[0], vol[0]), scale(cen[1], vol[1])), 1.0 / (vol[0] + vol[1]));
+    const V3 pts5[5] = {P[0], P[1], P[2], bc[0], bc[1]};
+    real h = 0.0;
+    for (int a = 0; a < 5; ++a)
+        for (int b = a + 1; b < 5; ++b) h = std::max(h, 0.5 * norm(sub(pts5[a], pts5[b])));
+
+    out.M.assign(N * N, 0.0);
+    for (int s = 0; s < 2; ++s) out.Q[s].assign(3 * N * N, 0.0);
+    const Rule& tr = tet_rule(p * p + (3 * p - 1) / 2);      // exact for degree 2p^2 + 3p - 3
+    for (int s = 0; s < 2; ++s) {
+        const Affine sa(std::array<V3, 4>{bref, ref[s][0], ref[s][1], ref[s][2]});
+        const real jsub = std::fabs(sa.det);
+        for (size_t q = 0; q < tr.w.size(); ++q) {
+            V3 x;
+            map(s, sa.to_phys(tr.pts[q]), x);
+            const real w = tr.w[q] * jsub * std::fabs(inv3(J, Ji));
+            taylor_eval(ex, x, x0, h, ps.data());
+            for (int k = 0; k < N; ++k)          // J^-T grad_xi
+                for (int d = 0; d < 3; ++d)
+                    gx[3 * k + d] = Ji[0 * 3 + d] * grad[3 * k + 0] + Ji[1 * 3 + d] * grad[3 * k + 1] +
+                                    Ji[2 * 3 + d] * grad[3 * k + 2];
+            for (int a = 0; a < N; ++a) {
+                const real wa = w * ps[a];
+                for (int b = 0; b < N; ++b) out.M[a * N + b] += wa * ps[b];
+                for (int d = 0; d < 3; ++d)
+                    for (int b = 0; b < N; ++b) out.Q[s][(d * N + a) * N + b] += wa * gx[3 * b + d];
+            }
+        }
+    }
+    // face part: - int_Gamma psi phi_i n_ij dS, n dS = +-(t_u x t_v) du dv
+    const V3 e1 = sub(ref[0][1], ref[0][0]), e2 = sub(ref[0][2], ref[0][0]);
+    V3 nref = cross(e1, e2);                                   // reference normal out of t
+    if (dot(nref, sub(ref[0][0], kRefVert[f])) < 0) nref = scale(nref, -1.0);
+    const Rule& fr = tri_rule(p * (p + 3) / 2);               // exact for degree p^2 + 3p - 2
+    for (size_t q = 0; q < fr.w.size(); ++q) {
+        const real lam[3] = {1 - fr.pts[q][0] - fr.pts[q][1], fr.pts[q][0], fr.pts[q][1]};
+        V3 xi[2] = {{0, 0, 0}, {0, 0, 0}};
+        for (int s = 0; s < 2; ++s)
+            for (int i = 0; i < 3; ++i) xi[s] = add(xi[s], scale(ref[s][i], lam[i]));
+        V3 x, x1;
+        map(1, xi[1], x1);
+        std::copy(val.begin(), val.end(), ph[1].begin());
+        map(0, xi[0], x);
+        std::copy(val.begin(), val.end(), ph[0].begin());
+        if (norm(sub(x, x1)) > 1e-9 * h) return -2;
+        inv3(J, Ji);
+        V3 tu, tv;
+        for (int r = 0; r < 3; ++r) {
+            tu[r] = J[r * 3 + 0] * e1[0] + J[r * 3 + 1] * e1[1] + J[r * 3 + 2] * e1[2];
+            tv[r] = J[r * 3 + 0] * e2[0] + J[r * 3 + 1] * e2[1] + J[r * 3 + 2] * e2[2];
+        }
+        V3 A = cross(tu, tv);
+        V3 ng;                                                 // J^-T n_ref points out of t
+        for (int d = 0; d < 3; ++d) ng[d] = Ji[0 * 3 + d] * nref[0] + Ji[1 * 3 + d] * nref[1] + Ji[2 * 3 + d] * nref[2];
+        if (dot(A, ng) < 0) A = scale(A, -1.0);
+        taylor_eval(ex, x, x0, h, ps.data());
+        for (int s = 0; s < 2; ++s) {
+            const real sg = (s == 0) ? 1.0 : -1.0;
+            for (int a = 0; a < N; ++a)
+                for (int d = 0; d < 3; ++d) {
+                    const real c = fr.w[q] * ps[a] * sg * A[d];
+                    for (int b = 0; b < N; ++b) out.Q[s][(d * N + a) * N + b] -= c * ph[s][b];
+                }
+        }
+    }
+    return 0;
+}
 
 // Five dt^2-scaled spatial blocks of element t: [0] diagonal, [1+f] coupling
 // to the neighbour across local face f (zero on a boundary face).
@@ -178,7 +326,20 @@ static int element_blocks(const stdg_mesh* m, int64_t t, const NodalBasis& phi, 
         const V3 sh = neighbour_shift(m, t, f);
         std::array<V3, 4> Vk = m->vert[k];
         for (auto& v : Vk) v = add(v, sh);
-        dual_face_blocks(phi, m->p, m->vert[t], f, Vk, fb);
+        if (m->curved && (m->bent[t] || m->bent[k])) {
+            int kv[3];
+            for (int a = 0, n = 0; a < 4; ++a) {
+                if (a == f) continue;
+                int best = 0;
+                for (int b = 1; b < 4; ++b)
+                    if (norm(sub(Vk[b], m->vert[t][a])) < norm(sub(Vk[best], m->vert[t][a]))) best = b;
+                kv[n++] = best;
+            }
+            if (curved_face_blocks(phi, m->p, m->geo.data() + t * N, f, m->geo.data() + k * N, sh, kv, fb) != 0)
+                return -2;
+        } else {
+            dual_face_blocks(phi, m->p, m->vert[t], f, Vk, fb);
+        }
         std::vector<real> L = fb.M;
         if (!cholesky(N, L)) return -1;
         for (int s = 0; s < 2; ++s) {
@@ -377,9 +538,24 @@ int assign_classes(stdg_mesh* m, std::vector<int64_t>& rep) {
     std::map<std::vector<int64_t>, int> classes;
     rep.clear();
     m->cls.resize(E);
+    auto touches_bent = [&](int64_t t) {
+        if (!m->curved) return false;
+        if (m->bent[t]) return true;
+        for (int f = 0; f < 4; ++f)
+            if (m->nbr[4 * t + f] >= 0 && m->bent[m->nbr[4 * t + f]]) return true;
+        return false;
+    };
     for (int64_t t = 0; t < E; ++t) {
         std::vector<int64_t> key;
         key.reserve(3 * 3 + 4 * 13);
+        if (touches_bent(t)) {
+            // a curved element or a neighbour of one: its blocks are its own
+            key = {INT64_MAX, t};
+            auto it = classes.emplace(std::move(key), (int)rep.size()).first;
+            rep.push_back(t);
+            m->cls[t] = it->second;
+            continue;
+        }
         const V3 v0 = m->vert[t][0];
         for (int a = 1; a < 4; ++a)
             for (int d = 0; d < 3; ++d) key.push_back(std::llround((m->vert[t][a][d] - v0[d]) / quantum));
@@ -451,14 +627,62 @@ std::vector<int64_t> class_chunk_order(const stdg_mesh* m) {
     return order;
 }
 
+// Nodes of curved elements (input order [n_tet][N][3]) into internal order;
+// the vertex nodes must be the vertices, and an element is bent when some
+// node lies off the affine image of its reference position.
+int set_geometry(stdg_mesh* m, const double* nodes) {
+    const int N = m->N, p = m->p;
+    const int64_t E = m->E;
+    const auto ex = exponents(p);
+    int vnode[4] = {0, 0, 0, 0};
+    for (int k = 0; k < N; ++k) {
+        if (ex[k][0] == p) vnode[1] = k;
+        if (ex[k][1] == p) vnode[2] = k;
+        if (ex[k][2] == p) vnode[3] = k;
+    }
+    m->geo.resize((size_t)E * N);
+    m->bent.assign(E, 0);
+    int64_t bad = -1, nbent = 0;
+    for (int64_t t = 0; t < E; ++t) {
+        const double* src = nodes + (size_t)m->perm[t] * N * 3;
+        V3* X = m->geo.data() + (size_t)t * N;
+        for (int k = 0; k < N; ++k) X[k] = {src[3 * k], src[3 * k + 1], src[3 * k + 2]};
+        const auto& v = m->vert[t];
+        real size = 0;
+        for (int a = 1; a < 4; ++a) size = std::max(size, norm(sub(v[a], v[0])));
+        for (int a = 0; a < 4; ++a)
+            if (norm(sub(X[vnode[a]], v[a])) > 1e-12 * size) bad = m->perm[t];
+        for (int k = 0; k < N && !m->bent[t]; ++k) {
+            V3 y = v[0];
+            for (int a = 1; a < 4; ++a) y = add(y, scale(sub(v[a], v[0]), (real)ex[k][a - 1] / p));
+            if (norm(sub(X[k], y)) > 1e-12 * size) m->bent[t] = 1;
+        }
+        nbent += m->bent[t];
+    }
+    if (bad >= 0) {
+        set_error("element " + std::to_string(bad) + ": vertex nodes do not match the vertices");
+        return STDG_ERR_MESH;
+    }
+    m->curved = nbent > 0;
+    if (!m->curved) {
+        m->geo.clear();
+        m->bent.clear();
+    }
+    return STDG_OK;
+}
+
 int build_blocks(stdg_mesh* m, const std::vector<int64_t>& rep) {
     const int N = m->N;
     m->blocks.assign((size_t)m->n_classes * 5 * N * N, 0.0);
     const NodalBasis phi(m->p);
-    int bad = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
-    for (int c = 0; c < m->n_classes; ++c)
-        if (element_blocks(m, rep[c], phi, m->blocks.data() + (size_t)c * 5 * N * N) != 0) bad++;
+    int bad = 0, open = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad, open)
+    for (int c = 0; c < m->n_classes; ++c) {
+        const int r = element_blocks(m, rep[c], phi, m->blocks.data() + (size_t)c * 5 * N * N);
+        bad += r == -1;
+        open += r == -2;
+    }
+    if (open) { set_error("curved elements do not share their common face (non-conforming nodes)"); return STDG_ERR_MESH; }
     if (bad) { set_error("dual mass matrix not positive definite (degenerate dual element)"); return STDG_ERR_MESH; }
     time_factor(m->G, m->Ctime);
     return STDG_OK;

@@ -739,8 +739,12 @@ extern "C" void stdg_step_opts_default(stdg_step_opts* o) {
     o->theta = 1.0;
 }
 
+static const char* kCurvedPicard =
+    "curved elements: only the pressure system is built, the Picard-step tables need affine elements";
+
 extern "C" int stdg_dual_from_main(const stdg_mesh* m, const double* vbar, double* vhat, void* stream) {
     if (!m || !vbar || !vhat) { set_error("null argument"); return STDG_ERR_ARG; }
+    if (m->curved) { set_error(kCurvedPicard); return STDG_ERR_ARG; }
     if (!m->d.blocks || !m->pd.GB) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
     const int64_t F = (int64_t)m->faces.size();
     const int64_t n = 3 * F * m->Nst;
@@ -751,6 +755,7 @@ extern "C" int stdg_dual_from_main(const stdg_mesh* m, const double* vbar, doubl
 
 extern "C" int stdg_main_from_dual(const stdg_mesh* m, const double* vhat, double* vbar, void* stream) {
     if (!m || !vbar || !vhat) { set_error("null argument"); return STDG_ERR_ARG; }
+    if (m->curved) { set_error(kCurvedPicard); return STDG_ERR_ARG; }
     if (!m->d.blocks || !m->pd.A) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
     const int64_t n = 3 * m->E * m->Nst;
     (void)n;
@@ -760,6 +765,7 @@ extern "C" int stdg_main_from_dual(const stdg_mesh* m, const double* vhat, doubl
 
 extern "C" int stdg_divergence(const stdg_mesh* m, const double* vhat, double* div, void* stream) {
     if (!m || !vhat || !div) { set_error("null argument"); return STDG_ERR_ARG; }
+    if (m->curved) { set_error(kCurvedPicard); return STDG_ERR_ARG; }
     if (!m->d.blocks || !m->pd.QT) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
     // sum_j D_ij vhat_j = -sum_j Q_ij^T vhat_j
     const int64_t n = m->E * m->Nst;
@@ -773,6 +779,7 @@ extern "C" int stdg_picard_step(const stdg_mesh* cm, double* vhat, double* vbar,
     auto t0 = std::chrono::steady_clock::now();
     if (!cm || !vhat || !vbar || !p || !opts) { set_error("null argument"); return STDG_ERR_ARG; }
     stdg_mesh* m = const_cast<stdg_mesh*>(cm);
+    if (m->curved) { set_error(kCurvedPicard); return STDG_ERR_ARG; }
     if (!m->d.blocks || !m->pd.A) { set_error("mesh was built host-only"); return STDG_ERR_ARG; }
     if (m->G > 5) { set_error("the Picard step is implemented for p_gamma <= 4"); return STDG_ERR_ARG; }
     const double theta = opts->theta;

@@ -133,3 +133,74 @@ def test_device_entry_points_reject_host_only_handle():
     lib = _lib.load()
     code = lib.stdg_pressure_apply(m._h, 0, ctypes.c_void_p(8), ctypes.c_void_p(16), None)
     assert code == _lib.STDG_ERR_ARG
+
+
+@pytest.mark.parametrize("n,p,pg,kind,eps,periodic", [
+    (2, 2, 0, "bulge", 0.15, False), (3, 2, 1, "periodic", 0.04, True),
+    (2, 2, 1, "quadratic", 0.2, False), (1, 3, 0, "bulge", 0.1, False)])
+def test_host_curved_tables_match_oracle(n, p, pg, kind, eps, periodic):
+    """Curved isoparametric elements (Sec. 2.8): the library's blocks, from its
+    own exact reference-coordinate integration, reproduce the oracle's curved
+    space-time operator."""
+    from oracle.curved import CurvedSpaceTimeOperators, IsoMesh
+    from stdg_inputs import curved_mesh, kuhn_mesh
+    X, T = kuhn_mesh(n)
+    Xc, nodes = curved_mesh(X, T, p, kind, eps)
+    m = P.Mesh(Xc, T, p, pg, dt=0.05, periodic=periodic, device=False, nodes=nodes)
+    assert m.n_classes == m.E                      # every element curved
+    ops = CurvedSpaceTimeOperators(IsoMesh(Xc, T, nodes, p, periodic=periodic), p, pg, 0.05)
+    x = np.random.default_rng(1).standard_normal((m.E, m.Nst))
+    yo = apply_S(ops, x)
+    perm = m.permutation()
+    yp = to_input(blocks_apply(m, x[perm]), perm)
+    tol = 1e-12 if p <= 2 else 1e-11              # the oracle's degree-25 rule has alternating weights
+    assert np.abs(yp - yo).max() <= tol * np.abs(yo).max()
+
+
+def test_host_curved_straight_nodes_and_partial_curving():
+    """Straight nodes give the straight mesh exactly; curving only the
+    elements of one hexahedron gives their blocks and their neighbours' their
+    own classes while the rest keep the shared ones."""
+    from stdg_inputs import curved_mesh, kuhn_mesh, node_coordinates
+    X, T = kuhn_mesh(3)
+    p = 2
+    a = P.Mesh(X, T, p, 0, dt=0.05, periodic=True, device=False)
+    b = P.Mesh(X, T, p, 0, dt=0.05, periodic=True, device=False, nodes=node_coordinates(X, T, p))
+    assert b.n_classes == a.n_classes == 6
+    for u, v in zip(a.blocks(), b.blocks()):
+        assert np.array_equal(u, v)
+    nodes = node_coordinates(X, T, p)
+    hexa = np.arange(6 * 13, 6 * 14)               # the central hexahedron [1/3, 2/3]^3
+    # a smooth displacement that vanishes outside the hexahedron, applied by
+    # position so shared nodes move together
+    u = np.clip((nodes - 1.0 / 3.0) * 3.0, 0.0, 1.0)
+    bump = np.prod(np.sin(np.pi * u), axis=-1, keepdims=True)
+    bump[bump < 1e-12] = 0.0                       # sin(pi) is not exactly zero
+    nodes = nodes + 0.02 * bump * np.array([1.0, -0.5, 0.3])
+    assert np.abs(bump[hexa]).max() > 0.5 and np.abs(np.delete(bump, hexa, axis=0)).max() == 0.0
+    c = P.Mesh(X, T, p, 0, dt=0.05, periodic=True, device=False, nodes=nodes)
+    assert 6 < c.n_classes < c.E
+    from oracle.curved import CurvedSpaceTimeOperators, IsoMesh
+    ops = CurvedSpaceTimeOperators(IsoMesh(X, T, nodes, p, periodic=True), p, 0, 0.05)
+    x = np.random.default_rng(3).standard_normal((c.E, c.Nst))
+    perm = c.permutation()
+    yp = to_input(blocks_apply(c, x[perm]), perm)
+    sample = sorted(set(hexa.tolist()) | {0, 50, 100, 161})
+    yo = apply_S(ops, x, elements=sample)
+    assert np.abs(yp[sample] - yo[sample]).max() <= 1e-12 * np.abs(yo[sample]).max()
+
+
+def test_curved_mesh_errors():
+    from stdg_inputs import curved_mesh, kuhn_mesh
+    X, T = kuhn_mesh(2)
+    Xc, nodes = curved_mesh(X, T, 2, "bulge", 0.1)
+    bad = nodes.copy()
+    bad[3, 0] += 1e-3                               # a vertex node off its vertex
+    with pytest.raises(RuntimeError, match="vertex nodes"):
+        P.Mesh(Xc, T, 2, 0, device=False, nodes=bad)
+    bad = nodes.copy()
+    bad[5, 1] += 1e-2                               # an edge node of one element only
+    with pytest.raises(RuntimeError, match="non-conforming"):
+        P.Mesh(Xc, T, 2, 0, device=False, nodes=bad)
+    with pytest.raises(ValueError):
+        P.Mesh(Xc, T, 2, 0, device=False, nodes=nodes[:, :5])
