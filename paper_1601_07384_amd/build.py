@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstdg.so")
 SOURCES = ["fem.cpp", "mesh.cpp", "picard_tables.cpp", "capi.cpp", "apply.hip", "krylov.hip",
-           "picard.hip", "mlp.hip", "cg_fused.hip", "cg_lane.hip", "picard_fast.hip"]
+           "picard.hip", "mlp.hip", "cg_fused.hip", "cg_lane.hip", "cg_elem.hip", "picard_fast.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fopenmp",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

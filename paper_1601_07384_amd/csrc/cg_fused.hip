@@ -525,6 +525,8 @@ hipError_t op_n(const stdg_mesh* m, float* x, const float* r_in, const float* p_
         if (ITER) return lane_iter_f32(m, x, r_in, p_in, q_in, r_out, p_out, q_out, ab, cscale, precond, part_out, s);
         return lane_apply_f32(m, r_in, q_out, cscale, s);
     }
+    if (ITER && elem_supported(m))
+        return elem_iter_f32(m, x, r_in, p_in, q_in, r_out, p_out, q_out, ab, cscale, precond, part_out, s);
     hipLaunchKernelGGL((k_cg_op<N, ITER>), dim3((unsigned)tile_blocks(m)), dim3(64 * WPB), 0, s, m->d.aop32, m->d.cls,
                        m->d.nbr, x, r_in, p_in, q_in, r_out, p_out, q_out, ab, cscale, precond, (int32_t)m->E,
                        (int32_t)m->G, g_multiplier(m), vbytes, part_out);
@@ -604,12 +606,14 @@ int upload_cg_operands(stdg_mesh* m) {
     m->d.cg_precond_ok = spd ? 1 : 0;
     STDG_HIP(hipMalloc(&m->d.aop32, t.size() * sizeof(float)));
     STDG_HIP(hipMemcpy(m->d.aop32, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
-    return upload_lane_operands(m, invs);
+    const int e = upload_lane_operands(m, invs);
+    if (e != STDG_OK || lane_supported(m)) return e;
+    return upload_elem_operands(m, invs);
 }
 
 // workgroups (and partial records) of one CG iteration launch
 int64_t cg_op_blocks(const stdg_mesh* m) {
-    return lane_supported(m) ? lane_iter_blocks(m) : tile_blocks(m);
+    return lane_supported(m) ? lane_iter_blocks(m) : (elem_supported(m) ? elem_iter_blocks(m) : tile_blocks(m));
 }
 
 int64_t cg_partial_len(const stdg_mesh* m) { return PSTRIDE * cg_op_blocks(m); }

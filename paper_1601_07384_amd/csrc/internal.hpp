@@ -41,6 +41,7 @@ struct DeviceTables {
     int32_t* chunk_halo = nullptr;  // [chunks][chunk_hmax] element of halo row h, -1 padding
     int chunk_hmax = 0;             // halo rows per chunk (multiple of 64)
     int64_t chunk_chunks = 0;
+    float* elem_ops = nullptr;    // per-element FP32 blocks of the per-element PCG iteration (null: not used)
     float* lane_ops = nullptr;    // class operands of the element-per-lane kernels (null: a run mixes classes)
     int runs_uniform = 0;         // every 64-element run of the element order holds one class
     int32_t* cls = nullptr;       // [E]
