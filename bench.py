@@ -32,12 +32,14 @@ guess).
 
 The roofline entry is for the step's dominant kernel, the one-kernel FP32 CG
 iteration (k_lane_chunk<N> on meshes whose 64-element runs share a geometry
-class, k_cg_op<N, true> otherwise), together with the one-block scalar kernel
-k_cg_red that precedes each launch.  Its duration per iteration is the
+class, k_elem_iter<N, G> on meshes whose elements mostly carry their own
+blocks, k_cg_op<N, true> otherwise), together with the one-block scalar
+kernel k_cg_red that precedes each launch.  Its duration per iteration is the
 library's own HIP-event measurement on its stream around the back-to-back
 iteration launches of the timed steps (stdg_step_report.pressure_fused_iter_us).
 Algorithmic bytes per iteration: read z, p, w, x and write them once (8 x 4 B
-per DoF) plus 20 B of indices per element.
+per DoF) plus 20 B of indices per element, plus, for k_elem_iter, the six
+FP32 N x N blocks of every element (24 N^2 B per element).
 """
 
 import argparse
@@ -399,7 +401,7 @@ def main():
     # one-kernel FP32 CG iteration (B (x) I): z, p, w, x read and written once
     it_us = sum(r.pressure_fused_iter_us * r.pressure_iters for r in reps) / max(
         sum(r.pressure_iters for r in reps if r.pressure_fused_iter_us > 0), 1)
-    k_bytes = 8.0 * dofs * 4 + 20.0 * E
+    k_bytes = 8.0 * dofs * 4 + 20.0 * E + (24.0 * N * N * E if m.inner_per_element else 0.0)
     k_flops = 2.0 * N * N * 5 * E * G
     k_s = it_us * 1e-6 if it_us > 0 else float("nan")
     first = reps[0]
@@ -434,7 +436,8 @@ def main():
                      "unit": "GB/s", "frac": k_bytes / k_s / 1e9 / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.config) if args.jitter == 0 else None,
                      "kernel": (f"k_lane_chunk<{N}> + k_cg_red (one PCG iteration)" if run_layout
-                                else f"k_cg_op<{N},true> + k_cg_red (one PCG iteration)"), "kernel_us": it_us,
+                                else (f"k_elem_iter<{N},{G}> + k_cg_red (one PCG iteration)" if m.inner_per_element
+                                      else f"k_cg_op<{N},true> + k_cg_red (one PCG iteration)")), "kernel_us": it_us,
                      "kernel_launches": sum(r.pressure_iters for r in reps),
                      "bytes_per_launch": k_bytes, "flops_per_launch": k_flops,
                      "mfma_tflops": k_flops / k_s / 1e12,

@@ -97,6 +97,10 @@ typedef struct {
     int32_t inner_layout;       /* STDG_LAYOUT_ELEMENT or STDG_LAYOUT_RUN:    */
                                 /* layout of the FP32 inner-solve vectors     */
     int64_t inner_len;          /* floats in one such vector                  */
+    int32_t inner_per_element;  /* 1: the FP32 PCG iteration streams a table  */
+                                /* of 6 N x N FP32 blocks per element (meshes */
+                                /* whose elements mostly have their own       */
+                                /* blocks: unstructured or curved)            */
 } stdg_mesh_info;
 
 /* Layouts of FP32 vectors of the inner (refinement) solve.

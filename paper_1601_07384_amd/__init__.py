@@ -111,6 +111,7 @@ class Mesh:
         self.n_classes = info.n_classes
         self.anchor_internal = info.anchor_internal
         self.inner_layout, self.inner_len = info.inner_layout, info.inner_len
+        self.inner_per_element = bool(info.inner_per_element)
         self.p, self.p_gamma, self.dt, self.nu = p, p_gamma, dt, nu
 
     def __del__(self):

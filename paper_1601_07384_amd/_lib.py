@@ -41,7 +41,8 @@ class MeshInfo(ctypes.Structure):
                 ("n_interior_face", ctypes.c_int64),
                 ("N", ctypes.c_int32), ("G", ctypes.c_int32), ("Nst", ctypes.c_int32),
                 ("n_classes", ctypes.c_int32), ("anchor_internal", ctypes.c_int64),
-                ("inner_layout", ctypes.c_int32), ("inner_len", ctypes.c_int64)]
+                ("inner_layout", ctypes.c_int32), ("inner_len", ctypes.c_int64),
+                ("inner_per_element", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):

@@ -187,6 +187,7 @@ extern "C" int stdg_mesh_info_get(const stdg_mesh* m, stdg_mesh_info* info) {
     const bool run = lane_supported(m);
     info->inner_layout = run ? STDG_LAYOUT_RUN : STDG_LAYOUT_ELEMENT;
     info->inner_len = run ? lane_len(m) : m->E * m->G * m->N;
+    info->inner_per_element = m->d.elem_ops != nullptr ? 1 : 0;
     return STDG_OK;
 }
 

@@ -284,6 +284,10 @@ SOLVE = [  # n, p, pg, periodic, jitter, method, precision
     (8, 2, 0, True, 0.0, P.STDG_CG, P.STDG_FP32),     # chunk-staged FP32 PCG, 8 chunks with halos
     (8, 3, 0, True, 0.0, P.STDG_CG, P.STDG_FP32),     # the same at the headline degree (N = 20)
     (2, 4, 1, False, 0.0, P.STDG_CG_TIME, P.STDG_FP32),   # p = 4: FP32 refinement, element-major layout
+    # jittered: every element its own blocks, the per-element PCG iteration
+    # (k_elem_iter) at N = 20, 10, 4 with two time nodes
+    (3, 3, 1, False, 0.1, P.STDG_CG_TIME, P.STDG_FP32),
+    (3, 1, 1, True, 0.1, P.STDG_CG_TIME, P.STDG_FP32),
 ]
 
 
@@ -301,6 +305,8 @@ def test_solve_matches_oracle(n, p, pg, periodic, jitter, method, precision):
     b = S @ xt + 1e-3 * np.abs(S @ xt).max() * rng.standard_normal(S.shape[0])
     xo = solve_anchored(ops, S, b).reshape(m.E, m.Nst)
     perm = m.permutation()
+    if jitter and precision == P.STDG_FP32 and p <= 3:
+        assert m.inner_per_element                    # the per-element iteration runs
     bg = gpu(b.reshape(m.E, m.Nst)[perm].ravel())
     xg = torch.zeros_like(bg)
     rep = m.solve(bg, xg, method=method, precision=precision, rtol=1e-12, restart=40)
