@@ -307,6 +307,128 @@ __global__ void __launch_bounds__(64) schur_apply_run(const double* __restrict__
     }
 }
 
+// FP64 apply on the FP64 matrix cores, meshes whose 64-element runs share a
+// class.  v_mfma_f64_4x4x4f64 runs four independent 4 x 4 x 4 products
+// (blocks b = 0..3); lane 16 k + 4 b + i holds A_b[i][k], lane 16 k + 4 b + j
+// holds B_b[k][j], and D_b[i][j] lands in lane 16 i + 4 b + j (probed on the
+// GPU; the broadcast fields have no effect on this instruction, so the A
+// operand is simply the same in the four blocks).  One 256-thread workgroup
+// per run: the class's five blocks are staged in LDS, zero-padded to
+// NP = 4 ceil(N / 4) rows and columns; wavefront w takes elements
+// 16 w .. 16 w + 15 of the run as the 16 columns (element 4 b + j in lanes
+// 16 k + 4 b + j), so a lane's column is the same element in the B operand
+// and in the result.  Per (block, four-column step ks, four-row group rg) an
+// instruction adds B_k[4 rg .. +3][4 ks .. +3] x[4 ks .. +3] to rows
+// 4 rg .. +3 of the 16 elements, for each time node: the A value comes from
+// LDS (lane 16 k + 4 b + i reads B_k[4 rg + i][4 ks + k]), the B value is
+// one double of the neighbour's row (four lanes of a column read 32
+// consecutive bytes).  No padding at N = 4, 20; the G x G time factor is
+// applied to the G accumulators of a lane, which hold one row of one element
+// for every time node.
+template <int N, int G, int CW>
+__global__ void __launch_bounds__(256 / CW) schur_apply_mfma(const double* __restrict__ BT,
+                                                             const int32_t* __restrict__ cls,
+                                                             const int32_t* __restrict__ nbr,
+                                                             const double* __restrict__ C, const double* x,
+                                                             double* __restrict__ y, int64_t E, uint32_t n_runs,
+                                                             uint32_t xbytes) {
+    constexpr int NQ = (N + 3) / 4, NP = 4 * NQ, NT = 256 / CW;
+    constexpr uint32_t OOBX = 0x80000000u;
+    __shared__ double A[5 * NP * NP];
+    const uint32_t run = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    if (run >= n_runs) return;                          // uniform over the workgroup
+    const int64_t e0 = (int64_t)run * 64;
+    const int c = __builtin_amdgcn_readfirstlane(cls[e0]);
+    // A[k][r][col] = B_k[r][col] = BT[c][k][col][r] (r fastest: contiguous reads)
+    for (int t = threadIdx.x; t < 5 * NP * NP; t += NT) {
+        const int r = t % NP, col = (t / NP) % NP, k = t / (NP * NP);
+        A[(k * NP + r) * NP + col] = (r < N && col < N) ? BT[(((int64_t)c * 5 + k) * N + col) * N + r] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int hi = lane >> 4, lo = lane & 3;            // k (B) / i (D) and i (A) / j
+    // column group g of this wavefront: elements 16 (CW w + g) + 4 b + j
+    int64_t e[CW];
+    bool valid[CW];
+    int nb[CW][4];
+#pragma unroll
+    for (int g = 0; g < CW; ++g) {
+        e[g] = e0 + 16 * (CW * w + g) + 4 * ((lane >> 2) & 3) + lo;
+        valid[g] = e[g] < E;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) nb[g][f] = valid[g] ? nbr[4 * e[g] + f] : -1;
+    }
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(x), (short)0,
+                                                                        (int)xbytes, 0x00020000);
+    double acc[NQ][CW][G];
+#pragma unroll
+    for (int rg = 0; rg < NQ; ++rg)
+#pragma unroll
+        for (int g = 0; g < CW; ++g)
+#pragma unroll
+            for (int a = 0; a < G; ++a) acc[rg][g][a] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        uint32_t base[CW];
+#pragma unroll
+        for (int g = 0; g < CW; ++g) {
+            const int64_t src = k == 0 ? (valid[g] ? e[g] : -1) : nb[g][k - 1];
+            base[g] = src >= 0 ? (uint32_t)src * (uint32_t)(G * N * 8) : OOBX;
+        }
+#pragma unroll
+        for (int ks = 0; ks < NQ; ++ks) {
+            const int col = 4 * ks + hi;
+            double bv[CW][G];
+#pragma unroll
+            for (int g = 0; g < CW; ++g)
+#pragma unroll
+                for (int a = 0; a < G; ++a) {
+                    const uint32_t off =
+                        (base[g] != OOBX && col < N) ? base[g] + (uint32_t)((a * N + col) * 8) : OOBX;
+                    bv[g][a] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rx, (int)off, 0, 0));
+                }
+#pragma unroll
+            for (int rg = 0; rg < NQ; ++rg) {
+                const double av = A[(k * NP + 4 * rg + lo) * NP + 4 * ks + hi];
+#pragma unroll
+                for (int g = 0; g < CW; ++g)
+#pragma unroll
+                    for (int a = 0; a < G; ++a)
+                        acc[rg][g][a] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bv[g][a], acc[rg][g][a], 0, 0, 0);
+            }
+        }
+    }
+    double Cm[G][G];
+#pragma unroll
+    for (int a = 0; a < G; ++a)
+#pragma unroll
+        for (int b = 0; b < G; ++b) Cm[a][b] = C[a * G + b];
+#pragma unroll
+    for (int g = 0; g < CW; ++g)
+        if (valid[g])
+#pragma unroll
+            for (int rg = 0; rg < NQ; ++rg) {
+                const int row = 4 * rg + hi;
+                if (row < N)
+#pragma unroll
+                    for (int a = 0; a < G; ++a) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int b = 0; b < G; ++b) s += Cm[a][b] * acc[rg][g][b];
+                        y[(e[g] * G + a) * N + row] = s;
+                    }
+            }
+}
+
+template <int N, int G, int CW>
+static hipError_t launch_mfma(const stdg_mesh* m, const double* C, const double* x, double* y, hipStream_t s) {
+    const uint32_t runs = (uint32_t)((m->E + 63) / 64);
+    const uint32_t blocks = (runs + 7) / 8 * 8;
+    hipLaunchKernelGGL((schur_apply_mfma<N, G, CW>), dim3(blocks), dim3(256 / CW), 0, s, m->d.blocks, m->d.cls,
+                       m->d.nbr, C, x, y, m->E, runs, (uint32_t)(8 * m->E * m->G * m->N));
+    return hipGetLastError();
+}
+
 template <int N, int G>
 static hipError_t launch_run(const stdg_mesh* m, const double* C, const double* x, double* y, hipStream_t s) {
     const uint32_t runs = (uint32_t)((m->E + 63) / 64);
@@ -360,12 +482,17 @@ static hipError_t launch_apply(const stdg_mesh* m, const T* BT, const T* C, cons
     // the 82,944 / 24,576-element meshes), the direct-gather kernel elsewhere
     // and for FP32 everywhere.
     if constexpr (sizeof(T) == 8) {
+        // measured on MI355X (HIP events, median): 663,552-element p = 3 cube 174 (tn) -> 118 us
+        // (two 16-element column groups per wavefront), 82,944-element p = 3, p_gamma = 1 cube
+        // 92 (lds) -> 35 us; at p = 2 the MFMA kernel (32 us) only ties the run kernel
+        if (m->d.runs_uniform && 8 * m->E * m->G * m->N < (int64_t(1) << 31)) {
+            if (m->N == 20 && m->G == 1) return launch_mfma<20, 1, 2>(m, C, x, y, s);
+            if (m->N == 20 && m->G == 2) return launch_mfma<20, 2, 1>(m, C, x, y, s);
+        }
         if (m->d.runs_uniform && m->E < (int64_t(1) << 31)) {
 #define STDG_NG(n, g) \
     if (m->N == n && m->G == g) return launch_run<n, g>(m, C, x, y, s);
-            // measured on MI355X: 196,608-element p = 2, p_gamma = 1 cube 54 -> 32 us; at N = 20 the
-            // scalar operand stream (one FMA per scalar value and lane) makes it slower than the
-            // kernels below (663,552 elements, G = 1: 186 vs 170 us; 82,944, G = 2: 137 vs 92 us)
+            // measured on MI355X: 196,608-element p = 2, p_gamma = 1 cube 54 -> 32 us
             STDG_NG(4, 1) STDG_NG(4, 2) STDG_NG(10, 1) STDG_NG(10, 2)
 #undef STDG_NG
         }
