@@ -210,6 +210,42 @@ __global__ void __launch_bounds__(256) schur_apply_rows(
     }
 }
 
+// The rows kernel over a list of elements (the runs of several classes that
+// the matrix-core kernel leaves out).
+template <int G>
+__global__ void __launch_bounds__(256) schur_apply_list(
+    const double* __restrict__ BT, const int32_t* __restrict__ cls, const int32_t* __restrict__ nbr,
+    const double* __restrict__ C, const double* __restrict__ x, double* __restrict__ y,
+    const int32_t* __restrict__ elems, int64_t n_elems, int N) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t idx = gid / N;
+    const int n = (int)(gid - idx * N);
+    if (idx >= n_elems) return;
+    const int64_t i = elems[idx];
+    const double* Bc = BT + (int64_t)cls[i] * 5 * N * N;
+    double acc[G];
+#pragma unroll
+    for (int b = 0; b < G; ++b) acc[b] = 0.0;
+    for (int k = 0; k < 5; ++k) {
+        const int64_t t = (k == 0) ? i : (int64_t)nbr[4 * i + (k - 1)];
+        if (t < 0) continue;
+        const double* xt = x + t * G * N;
+        for (int mm = 0; mm < N; ++mm) {
+            const double bv = Bc[((int64_t)k * N + mm) * N + n];
+#pragma unroll
+            for (int b = 0; b < G; ++b) acc[b] += bv * xt[b * N + mm];
+        }
+    }
+    double* yi = y + i * G * N;
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < G; ++b) s += C[a * G + b] * acc[b];
+        yi[a * N + n] = s;
+    }
+}
+
 // Element-per-lane FP64 apply for meshes whose 64-element runs share a class
 // (the structured cubes).  One wavefront (and workgroup) per run, lane l =
 // element 64 run + l; for each of the five couplings the wavefront first
@@ -327,7 +363,7 @@ __global__ void __launch_bounds__(64) schur_apply_run(const double* __restrict__
 // for every time node.
 template <int N, int G, int CW>
 __global__ void __launch_bounds__(256 / CW) schur_apply_mfma(const double* __restrict__ BT,
-                                                             const int32_t* __restrict__ cls,
+                                                             const int32_t* __restrict__ run_cls,
                                                              const int32_t* __restrict__ nbr,
                                                              const double* __restrict__ C, const double* x,
                                                              double* __restrict__ y, int64_t E, uint32_t n_runs,
@@ -337,8 +373,9 @@ __global__ void __launch_bounds__(256 / CW) schur_apply_mfma(const double* __res
     __shared__ double A[5 * NP * NP];
     const uint32_t run = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
     if (run >= n_runs) return;                          // uniform over the workgroup
+    const int c = run_cls[run];                         // runs of several classes: schur_apply_list
+    if (c < 0) return;
     const int64_t e0 = (int64_t)run * 64;
-    const int c = __builtin_amdgcn_readfirstlane(cls[e0]);
     // A[k][r][col] = B_k[r][col] = BT[c][k][col][r] (r fastest: contiguous reads)
     for (int t = threadIdx.x; t < 5 * NP * NP; t += NT) {
         const int r = t % NP, col = (t / NP) % NP, k = t / (NP * NP);
@@ -367,12 +404,12 @@ __global__ void __launch_bounds__(256 / CW) schur_apply_mfma(const double* __res
         for (int g = 0; g < CW; ++g)
 #pragma unroll
             for (int a = 0; a < G; ++a) acc[rg][g][a] = 0.0;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
+    auto couple = [&](int k) {
         uint32_t base[CW];
 #pragma unroll
         for (int g = 0; g < CW; ++g) {
-            const int64_t src = k == 0 ? (valid[g] ? e[g] : -1) : nb[g][k - 1];
+            const int64_t src = k == 0 ? (valid[g] ? e[g] : -1)
+                                       : (k == 1 ? nb[g][0] : (k == 2 ? nb[g][1] : (k == 3 ? nb[g][2] : nb[g][3])));
             base[g] = src >= 0 ? (uint32_t)src * (uint32_t)(G * N * 8) : OOBX;
         }
 #pragma unroll
@@ -397,6 +434,15 @@ __global__ void __launch_bounds__(256 / CW) schur_apply_mfma(const double* __res
                         acc[rg][g][a] = __builtin_amdgcn_mfma_f64_4x4x4f64(av, bv[g][a], acc[rg][g][a], 0, 0, 0);
             }
         }
+    };
+    // large blocks (p = 4) one coupling at a time, so that the loads of the
+    // next coupling are not all held at once
+    if constexpr (NQ * G * CW > 16) {
+#pragma unroll 1
+        for (int k = 0; k < 5; ++k) couple(k);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) couple(k);
     }
     double Cm[G][G];
 #pragma unroll
@@ -424,8 +470,13 @@ template <int N, int G, int CW>
 static hipError_t launch_mfma(const stdg_mesh* m, const double* C, const double* x, double* y, hipStream_t s) {
     const uint32_t runs = (uint32_t)((m->E + 63) / 64);
     const uint32_t blocks = (runs + 7) / 8 * 8;
-    hipLaunchKernelGGL((schur_apply_mfma<N, G, CW>), dim3(blocks), dim3(256 / CW), 0, s, m->d.blocks, m->d.cls,
-                       m->d.nbr, C, x, y, m->E, runs, (uint32_t)(8 * m->E * m->G * m->N));
+    hipLaunchKernelGGL((schur_apply_mfma<N, G, CW>), dim3(blocks), dim3(256 / CW), 0, s, m->d.blocks,
+                       m->d.run_cls, m->d.nbr, C, x, y, m->E, runs, (uint32_t)(8 * m->E * m->G * m->N));
+    if (m->d.n_mixed_elems > 0) {
+        const int64_t work = m->d.n_mixed_elems * N;
+        hipLaunchKernelGGL((schur_apply_list<G>), dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, m->d.blocks,
+                           m->d.cls, m->d.nbr, C, x, y, m->d.mixed_elems, m->d.n_mixed_elems, N);
+    }
     return hipGetLastError();
 }
 
@@ -485,9 +536,18 @@ static hipError_t launch_apply(const stdg_mesh* m, const T* BT, const T* C, cons
         // measured on MI355X (HIP events, median): 663,552-element p = 3 cube 174 (tn) -> 118 us
         // (two 16-element column groups per wavefront), 82,944-element p = 3, p_gamma = 1 cube
         // 92 (lds) -> 35 us; at p = 2 the MFMA kernel (32 us) only ties the run kernel
-        if (m->d.runs_uniform && 8 * m->E * m->G * m->N < (int64_t(1) << 31)) {
+        // runs of several classes (Dirichlet meshes: their boundary-class tails) go to the
+        // list kernel; the matrix-core kernel is used while they are at most a quarter of
+        // the runs (16^3 Dirichlet cube: 12 of 384)
+        const int64_t runs = (m->E + 63) / 64;
+        if (4 * m->d.n_mixed_runs <= runs && 8 * m->E * m->G * m->N < (int64_t(1) << 31)) {
             if (m->N == 20 && m->G == 1) return launch_mfma<20, 1, 2>(m, C, x, y, s);
             if (m->N == 20 && m->G == 2) return launch_mfma<20, 2, 1>(m, C, x, y, s);
+            if (m->N == 35 && m->G == 1) return launch_mfma<35, 1, 2>(m, C, x, y, s);
+            if (m->N == 35 && m->G == 2) return launch_mfma<35, 2, 1>(m, C, x, y, s);
+            if (m->N == 35 && m->G == 3) return launch_mfma<35, 3, 1>(m, C, x, y, s);
+            if (m->N == 35 && m->G == 4) return launch_mfma<35, 4, 1>(m, C, x, y, s);
+            if (m->N == 35 && m->G == 5) return launch_mfma<35, 5, 1>(m, C, x, y, s);
         }
         if (m->d.runs_uniform && m->E < (int64_t(1) << 31)) {
 #define STDG_NG(n, g) \

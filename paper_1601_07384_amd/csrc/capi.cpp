@@ -32,10 +32,26 @@ int upload_tables(stdg_mesh* m) {
             }
     std::vector<float> c32(m->Ctime.begin(), m->Ctime.end());
     std::vector<int32_t> cls(m->cls.begin(), m->cls.end());
-    m->d.runs_uniform = 1;
-    for (int64_t t0 = 0; t0 < m->E && m->d.runs_uniform; t0 += 64)
-        for (int64_t e = t0 + 1; e < std::min<int64_t>(t0 + 64, m->E); ++e)
-            if (cls[e] != cls[t0]) { m->d.runs_uniform = 0; break; }
+    const int64_t runs = (m->E + 63) / 64;
+    std::vector<int32_t> run_cls(runs);
+    std::vector<int32_t> mixed;
+    for (int64_t r = 0; r < runs; ++r) {
+        const int64_t t0 = 64 * r, t1 = std::min<int64_t>(t0 + 64, m->E);
+        run_cls[r] = cls[t0];
+        for (int64_t e = t0 + 1; e < t1; ++e)
+            if (cls[e] != cls[t0]) run_cls[r] = -1;
+        if (run_cls[r] < 0)
+            for (int64_t e = t0; e < t1; ++e) mixed.push_back((int32_t)e);
+    }
+    m->d.n_mixed_runs = std::count(run_cls.begin(), run_cls.end(), -1);
+    m->d.runs_uniform = m->d.n_mixed_runs == 0 ? 1 : 0;
+    m->d.n_mixed_elems = (int64_t)mixed.size();
+    STDG_HIP(hipMalloc(&m->d.run_cls, runs * sizeof(int32_t)));
+    STDG_HIP(hipMemcpy(m->d.run_cls, run_cls.data(), runs * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!mixed.empty()) {
+        STDG_HIP(hipMalloc(&m->d.mixed_elems, mixed.size() * sizeof(int32_t)));
+        STDG_HIP(hipMemcpy(m->d.mixed_elems, mixed.data(), mixed.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     STDG_HIP(hipMalloc(&m->d.blocks, nb * sizeof(double)));
     STDG_HIP(hipMalloc(&m->d.blocks32, nb * sizeof(float)));
     STDG_HIP(hipMalloc(&m->d.cls, m->E * sizeof(int32_t)));
@@ -72,7 +88,7 @@ void free_tables(stdg_mesh* m) {
     for (void* p : {(void*)m->d.blocks, (void*)m->d.blocks32, (void*)m->d.aop32, (void*)m->d.cls, (void*)m->d.nbr,
                     (void*)m->d.C, (void*)m->d.C32, (void*)m->d.Cinv, (void*)m->d.Cinv32,
                     (void*)m->d.Cid, (void*)m->d.Cid32, (void*)m->d.chunk_slot, (void*)m->d.chunk_halo,
-                    (void*)m->d.lane_ops, (void*)m->d.elem_ops})
+                    (void*)m->d.lane_ops, (void*)m->d.elem_ops, (void*)m->d.run_cls, (void*)m->d.mixed_elems})
         if (p) (void)hipFree(p);
     m->d = DeviceTables();
 }

@@ -44,6 +44,10 @@ struct DeviceTables {
     float* elem_ops = nullptr;    // per-element FP32 blocks of the per-element PCG iteration (null: not used)
     float* lane_ops = nullptr;    // class operands of the element-per-lane kernels (null: a run mixes classes)
     int runs_uniform = 0;         // every 64-element run of the element order holds one class
+    int32_t* run_cls = nullptr;   // [runs] class of a one-class 64-element run, -1 for a run of several
+    int32_t* mixed_elems = nullptr;   // elements of the runs of several classes
+    int64_t n_mixed_elems = 0;
+    int64_t n_mixed_runs = 0;
     int32_t* cls = nullptr;       // [E]
     int32_t* nbr = nullptr;       // [E][4]  -1 on a boundary face
     double* C = nullptr;          // [G][G]  time factor W T^-1 W

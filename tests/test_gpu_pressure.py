@@ -117,6 +117,31 @@ def test_apply_c5_full_size_sampled_rows():
     assert _sampled_rows(32, 2, 1, True, 1e-3, 24, 8) <= 1e-12
 
 
+@pytest.mark.parametrize("n,p,pg", [(8, 4, 2), (8, 3, 1), (16, 3, 1)])
+def test_apply_dirichlet_mixed_runs_sampled_rows(n, p, pg):
+    """Dirichlet cubes: most 64-element runs hold one class (FP64 matrix-core
+    kernel), the boundary-class tails several (the list kernel); sampled rows
+    from both kinds of run against the oracle."""
+    print(f"case mixed runs n={n} p={p} pg={pg}", flush=True)
+    X, T = kuhn_mesh(n)
+    m = P.Mesh(X, T, p, pg, dt=1e-2)
+    _, cls, _, _ = m.blocks()
+    runs = (m.E + 63) // 64
+    mixed = [r for r in range(runs) if len(set(cls[64 * r:64 * (r + 1)].tolist())) > 1]
+    assert 0 < len(mixed) and 4 * len(mixed) <= runs
+    uniform = [r for r in range(runs) if r not in set(mixed)]
+    rng = np.random.default_rng(9)
+    internal = [64 * r + int(rng.integers(64)) for r in rng.choice(mixed, 4, replace=False)]
+    internal += [64 * r + int(rng.integers(64)) for r in rng.choice(uniform, 6, replace=False)]
+    perm = m.permutation()
+    rows = np.array([perm[i] for i in internal if i < m.E])
+    x = rng.standard_normal((m.E, m.Nst))
+    yg = to_input(lib_apply(m, x[perm]), perm)
+    ops = SpaceTimeOperators(OracleMesh(X, T), p, pg, 1e-2)
+    yo = apply_S(ops, x, elements=rows)
+    assert np.abs(yg[rows] - yo[rows]).max() <= 1e-12 * np.abs(yo[rows]).max()
+
+
 def _time_factor_inverse(pg):
     """C^-1 for C = W T^-1 W from the hand-derived time matrices (p_gamma <= 1)."""
     if pg == 0:
