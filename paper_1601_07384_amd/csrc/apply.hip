@@ -210,39 +210,49 @@ __global__ void __launch_bounds__(256) schur_apply_rows(
     }
 }
 
-// The rows kernel over a list of elements (the runs of several classes that
-// the matrix-core kernel leaves out).
+// The elements of the runs of several classes that the matrix-core kernel
+// leaves out: one workgroup of 5 N threads per element, thread (k, r)
+// forming row r of coupling k for every time node (the five couplings in
+// parallel, summed through LDS), then the G x G time factor.
 template <int G>
-__global__ void __launch_bounds__(256) schur_apply_list(
+__global__ void __launch_bounds__(5 * 35) schur_apply_list(
     const double* __restrict__ BT, const int32_t* __restrict__ cls, const int32_t* __restrict__ nbr,
     const double* __restrict__ C, const double* __restrict__ x, double* __restrict__ y,
-    const int32_t* __restrict__ elems, int64_t n_elems, int N) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t idx = gid / N;
-    const int n = (int)(gid - idx * N);
-    if (idx >= n_elems) return;
-    const int64_t i = elems[idx];
-    const double* Bc = BT + (int64_t)cls[i] * 5 * N * N;
+    const int32_t* __restrict__ elems, int N) {
+    __shared__ double part[5 * G * 35];
+    const int64_t i = elems[blockIdx.x];
+    const int k = threadIdx.x / N, r = threadIdx.x - k * N;
     double acc[G];
 #pragma unroll
     for (int b = 0; b < G; ++b) acc[b] = 0.0;
-    for (int k = 0; k < 5; ++k) {
-        const int64_t t = (k == 0) ? i : (int64_t)nbr[4 * i + (k - 1)];
-        if (t < 0) continue;
+    const int64_t t = (k == 0) ? i : (int64_t)nbr[4 * i + (k - 1)];
+    if (t >= 0) {
+        const double* Bk = BT + ((int64_t)cls[i] * 5 + k) * N * N;
         const double* xt = x + t * G * N;
         for (int mm = 0; mm < N; ++mm) {
-            const double bv = Bc[((int64_t)k * N + mm) * N + n];
+            const double bv = Bk[(int64_t)mm * N + r];
 #pragma unroll
             for (int b = 0; b < G; ++b) acc[b] += bv * xt[b * N + mm];
         }
     }
-    double* yi = y + i * G * N;
 #pragma unroll
-    for (int a = 0; a < G; ++a) {
-        double s = 0.0;
+    for (int b = 0; b < G; ++b) part[(k * G + b) * N + r] = acc[b];
+    __syncthreads();
+    if (k == 0) {
+        double z[G];
 #pragma unroll
-        for (int b = 0; b < G; ++b) s += C[a * G + b] * acc[b];
-        yi[a * N + n] = s;
+        for (int b = 0; b < G; ++b) {
+            z[b] = 0.0;
+            for (int kk = 0; kk < 5; ++kk) z[b] += part[(kk * G + b) * N + r];
+        }
+        double* yi = y + i * G * N;
+#pragma unroll
+        for (int a = 0; a < G; ++a) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < G; ++b) s += C[a * G + b] * z[b];
+            yi[a * N + r] = s;
+        }
     }
 }
 
@@ -472,11 +482,10 @@ static hipError_t launch_mfma(const stdg_mesh* m, const double* C, const double*
     const uint32_t blocks = (runs + 7) / 8 * 8;
     hipLaunchKernelGGL((schur_apply_mfma<N, G, CW>), dim3(blocks), dim3(256 / CW), 0, s, m->d.blocks,
                        m->d.run_cls, m->d.nbr, C, x, y, m->E, runs, (uint32_t)(8 * m->E * m->G * m->N));
-    if (m->d.n_mixed_elems > 0) {
-        const int64_t work = m->d.n_mixed_elems * N;
-        hipLaunchKernelGGL((schur_apply_list<G>), dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, m->d.blocks,
-                           m->d.cls, m->d.nbr, C, x, y, m->d.mixed_elems, m->d.n_mixed_elems, N);
-    }
+    static_assert(N <= 35, "list kernel: at most 5 x 35 threads per element");
+    if (m->d.n_mixed_elems > 0)
+        hipLaunchKernelGGL((schur_apply_list<G>), dim3((unsigned)m->d.n_mixed_elems), dim3(5 * N), 0, s, m->d.blocks,
+                           m->d.cls, m->d.nbr, C, x, y, m->d.mixed_elems, N);
     return hipGetLastError();
 }
 
