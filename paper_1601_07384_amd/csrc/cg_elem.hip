@@ -90,13 +90,14 @@ __device__ inline double wave_sum(double v) {
 // acc[k][a][rr] += rows R0 <= rr < R1 of this lane's slice of a block times
 // v[k][a] for the NV vectors and G time nodes (the block's entries are loaded
 // first, one coalesced 1 KB load per row and four columns of the wavefront)
-template <int N, int G, int NV, int R0, int R1>
+template <int N, int G, int NV, int R0, int R1, bool NT>
 __device__ __forceinline__ void block_rows(const f4* __restrict__ tb, const float (&v)[NV][G][N],
                                            float (&acc)[NV][G][ElemShape<N>::RPL]) {
     constexpr int NC4 = ElemShape<N>::NC4;
     f4 w[(R1 - R0) * NC4];
 #pragma unroll
-    for (int i = 0; i < (R1 - R0) * NC4; ++i) w[i] = __builtin_nontemporal_load(tb + 64 * (R0 * NC4 + i));
+    for (int i = 0; i < (R1 - R0) * NC4; ++i)
+        w[i] = NT ? __builtin_nontemporal_load(tb + 64 * (R0 * NC4 + i)) : tb[64 * (R0 * NC4 + i)];
 #pragma unroll
     for (int rr = R0; rr < R1; ++rr)
 #pragma unroll
@@ -116,16 +117,17 @@ __device__ __forceinline__ void block_rows(const f4* __restrict__ tb, const floa
 }
 
 // the whole slice, CR rows at a time, so that only CR rows of block entries
-// are held at once
-template <int N, int G, int NV, int R0 = 0>
+// are held at once; NT: streamed once (non-temporal loads), else kept in
+// the caches for a second pass
+template <int N, int G, int NV, int R0 = 0, bool NT = true>
 __device__ __forceinline__ void block_slice(const f4* __restrict__ tb, const float (&v)[NV][G][N],
                                             float (&acc)[NV][G][ElemShape<N>::RPL]) {
     constexpr int RPL = ElemShape<N>::RPL, CR = 2;
     constexpr int R1 = R0 + CR < RPL ? R0 + CR : RPL;
-    block_rows<N, G, NV, R0, R1>(tb, v, acc);
+    block_rows<N, G, NV, R0, R1, NT>(tb, v, acc);
     if constexpr (R1 < RPL) {
         __builtin_amdgcn_sched_barrier(0);
-        block_slice<N, G, NV, R1>(tb, v, acc);
+        block_slice<N, G, NV, R1, NT>(tb, v, acc);
     }
 }
 
@@ -170,7 +172,7 @@ __global__ void __launch_bounds__(64 * EWPB) k_elem_iter(
         const uint32_t own = valid ? (uint32_t)e * G * ROWB : OOB;
         const f4* tb = (const f4*)table + (size_t)wid * 6 * BSZ + lane;
         // own rows: z_i = z - alpha w, p_i = z_i + beta p; x += alpha p on the slice
-        float v2[2][G][N];                               // [0] p_i, [1] z_i of the own rows
+        float v1[1][G][N];                               // p_i of the own rows, then of a neighbour
         float zs[G][RPL], ps[G][RPL];
 #pragma unroll
         for (int a = 0; a < G; ++a) {
@@ -186,10 +188,7 @@ __global__ void __launch_bounds__(64 * EWPB) k_elem_iter(
             eslice_load<N>(rp, ro, r0, pl);
             eslice_load<N>(rx, ro, r0, xs);
 #pragma unroll
-            for (int r = 0; r < N; ++r) {
-                v2[1][a][r] = zo[r] - alpha * wo[r];
-                v2[0][a][r] = v2[1][a][r] + beta * po[r];
-            }
+            for (int r = 0; r < N; ++r) v1[0][a][r] = (zo[r] - alpha * wo[r]) + beta * po[r];
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
                 xs[i] += alpha * pl[i];
@@ -199,27 +198,19 @@ __global__ void __launch_bounds__(64 * EWPB) k_elem_iter(
             eslice_store<N>(rx, ro, r0, xs);
             __builtin_amdgcn_sched_barrier(0);
         }
-        // own block against p_i (the operator) and z_i (M z for the partial sums)
-        float acc2[2][G][RPL];
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-#pragma unroll
-            for (int a = 0; a < G; ++a)
-#pragma unroll
-                for (int i = 0; i < RPL; ++i) acc2[k][a][i] = 0.0f;
-        block_slice<N, G, 2>(tb, v2, acc2);
+        // own block against p_i, then the four neighbour blocks against the
+        // neighbours' p_i
         float acc[1][G][RPL];
 #pragma unroll
         for (int a = 0; a < G; ++a)
 #pragma unroll
-            for (int i = 0; i < RPL; ++i) acc[0][a][i] = acc2[0][a][i];
+            for (int i = 0; i < RPL; ++i) acc[0][a][i] = 0.0f;
+        block_slice<N, G, 1, 0, false>(tb, v1, acc);
         __builtin_amdgcn_sched_barrier(0);
-        // the four neighbour blocks against the neighbours' p_i
 #pragma unroll 1
         for (int f = 0; f < 4; ++f) {
             const int32_t k = f == 0 ? nb.x : (f == 1 ? nb.y : (f == 2 ? nb.z : nb.w));
             const uint32_t off = (valid && k >= 0) ? (uint32_t)k * G * ROWB : OOB;
-            float v1[1][G][N];
 #pragma unroll
             for (int a = 0; a < G; ++a) {
                 float zv[N], wv[N], pv[N];
@@ -234,18 +225,17 @@ __global__ void __launch_bounds__(64 * EWPB) k_elem_iter(
             block_slice<N, G, 1>(tb + (size_t)(1 + f) * BSZ, v1, acc);
             __builtin_amdgcn_sched_barrier(0);
         }
-        // w_i = B_e^-1 (B p_i): the whole row of B p_i from the element's L lanes
         float qv[G][RPL], rv[G][RPL], wn[1][G][RPL];
 #pragma unroll
         for (int a = 0; a < G; ++a)
 #pragma unroll
             for (int i = 0; i < RPL; ++i) {
                 qv[a][i] = cscale * acc[0][a][i];
-                rv[a][i] = precond ? cscale * acc2[1][a][i] : zs[a][i];
+                rv[a][i] = zs[a][i];
                 wn[0][a][i] = precond ? 0.0f : qv[a][i];
             }
         if (precond) {
-            float full[1][G][N];
+            // w_i = B_e^-1 (B p_i): the whole row of B p_i from the element's L lanes
             const int base = lane - q;
 #pragma unroll
             for (int qq = 0; qq < L; ++qq)
@@ -253,8 +243,32 @@ __global__ void __launch_bounds__(64 * EWPB) k_elem_iter(
                 for (int i = 0; i < RPL; ++i)
                     if (qq * RPL + i < N)
 #pragma unroll
-                        for (int a = 0; a < G; ++a) full[0][a][qq * RPL + i] = __shfl(acc[0][a][i], base + qq, 64);
-            block_slice<N, G, 1>(tb + (size_t)5 * BSZ, full, wn);
+                        for (int a = 0; a < G; ++a) v1[0][a][qq * RPL + i] = __shfl(acc[0][a][i], base + qq, 64);
+            block_slice<N, G, 1>(tb + (size_t)5 * BSZ, v1, wn);
+            __builtin_amdgcn_sched_barrier(0);
+            // r = M z_i = c B_e z_i for the partial sums: the own block again
+            // (from the cache) against z_i of the own rows, formed again from
+            // z and w (inputs of this launch, not overwritten by it)
+#pragma unroll
+            for (int a = 0; a < G; ++a) {
+                float zo[N], wo[N];
+                const uint32_t ro = own == OOB ? OOB : own + a * ROWB;
+                erow_load<N>(rz, ro, zo);
+                erow_load<N>(rw, ro, wo);
+#pragma unroll
+                for (int r = 0; r < N; ++r) v1[0][a][r] = zo[r] - alpha * wo[r];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            float ar[1][G][RPL];
+#pragma unroll
+            for (int a = 0; a < G; ++a)
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) ar[0][a][i] = 0.0f;
+            block_slice<N, G, 1, 0, false>(tb, v1, ar);
+#pragma unroll
+            for (int a = 0; a < G; ++a)
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) rv[a][i] = cscale * ar[0][a][i];
         }
         const Rsrc rqo = make_rsrc(q_out, vbytes), rro = make_rsrc(r_out, vbytes), rpo = make_rsrc(p_out, vbytes);
 #pragma unroll
