@@ -415,7 +415,8 @@ def main():
         "dtype": "f32 inner operator, f64 refinement", "data": "synthetic",
         "config": {"workload": workload_label(c, args.jitter), "pressure_dof": dofs,
                    "geometry_classes": m.n_classes},
-        "operator": {"kernel": (f"{'k_lane_op' if run_layout else 'k_cg_op'}<{N}> (FP32 B (x) I on MFMA)"
+        "operator": {"kernel": ((f"k_elem_op<{N},{G}> (FP32 B (x) I, per-element blocks)" if m.inner_per_element
+                                 else f"{'k_lane_op' if run_layout else 'k_cg_op'}<{N}> (FP32 B (x) I on MFMA)")
                                 if op32 is not None else "FP64 S x"), "median_us": inner_us,
                      "launches": args.applies,
                      "fp64_apply": {"median_us": fp64_us, "gdofs": dofs / fp64_us / 1e3,

@@ -305,6 +305,56 @@ __global__ void __launch_bounds__(64 * EWPB) k_elem_iter(
     }
 }
 
+// y = cscale (B (x) I) x on the same per-element tables (the operator of the
+// inner solve's residual and of stdg_pressure_apply_spatial_f32): the own
+// and four neighbour blocks against the rows of x, all time nodes per
+// wavefront, each lane storing its row slice.
+template <int N, int G>
+__global__ void __launch_bounds__(64 * EWPB) k_elem_op(const float* __restrict__ table,
+                                                       const int32_t* __restrict__ nbr, const float* x, float* y,
+                                                       float cscale, int32_t E, uint32_t n_waves, uint32_t vbytes) {
+    typedef ElemShape<N> S;
+    constexpr int L = S::L, RPL = S::RPL, EPW = S::EPW, NC4 = S::NC4;
+    constexpr uint32_t ROWB = 4u * N;
+    constexpr size_t BSZ = (size_t)RPL * NC4 * 64;
+    const uint32_t lblock = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    const uint32_t wid = lblock * EWPB + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wid >= n_waves) return;
+    const int lane = threadIdx.x & 63, q = lane % L, r0 = q * RPL;
+    const int32_t e = (int32_t)(wid * EPW) + lane / L;
+    const bool valid = e < E;
+    const Rsrc rn = make_rsrc(nbr, 16u * (uint32_t)E);
+    const i4v nb =
+        __builtin_bit_cast(i4v, __builtin_amdgcn_raw_buffer_load_b128(rn, (int)(valid ? 16u * e : OOB), 0, 0));
+    const Rsrc rx = make_rsrc(x, vbytes);
+    const f4* tb = (const f4*)table + (size_t)wid * 6 * BSZ + lane;
+    float acc[1][G][RPL];
+#pragma unroll
+    for (int a = 0; a < G; ++a)
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) acc[0][a][i] = 0.0f;
+#pragma unroll 1
+    for (int k = 0; k < 5; ++k) {
+        const int32_t src = k == 0 ? (valid ? e : -1) : (k == 1 ? nb.x : (k == 2 ? nb.y : (k == 3 ? nb.z : nb.w)));
+        const uint32_t off = src >= 0 ? (uint32_t)src * G * ROWB : OOB;
+        float v1[1][G][N];
+#pragma unroll
+        for (int a = 0; a < G; ++a) erow_load<N>(rx, off == OOB ? OOB : off + a * ROWB, v1[0][a]);
+        __builtin_amdgcn_sched_barrier(0);
+        block_slice<N, G, 1>(tb + (size_t)k * BSZ, v1, acc);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    const Rsrc ry = make_rsrc(y, vbytes);
+    const uint32_t own = valid ? (uint32_t)e * G * ROWB : OOB;
+#pragma unroll
+    for (int a = 0; a < G; ++a) {
+        float o[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) o[i] = cscale * acc[0][a][i];
+        eslice_store<N>(ry, own == OOB ? OOB : own + a * ROWB, r0, o);
+    }
+}
+
 template <int N> void elem_table(const stdg_mesh* m, const std::vector<double>& inv, std::vector<float>& out) {
     typedef ElemShape<N> S;
     constexpr int L = S::L, RPL = S::RPL, EPW = S::EPW, NC4 = S::NC4;
@@ -366,6 +416,23 @@ int upload_elem_operands(stdg_mesh* m, const std::vector<double>& inv) {
     STDG_HIP(hipMalloc(&m->d.elem_ops, t.size() * sizeof(float)));
     STDG_HIP(hipMemcpy(m->d.elem_ops, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
     return STDG_OK;
+}
+
+hipError_t elem_apply_f32(const stdg_mesh* m, const float* x, float* y, float cscale, hipStream_t s) {
+    const uint32_t vbytes = (uint32_t)(4 * m->E * m->G * m->N);
+    const dim3 grid((unsigned)elem_iter_blocks(m)), block(64 * EWPB);
+    const uint32_t nw = (uint32_t)elem_waves_n(m);
+#define STDG_NG(n, g)                                                                                           \
+    if (m->N == n && m->G == g) {                                                                               \
+        hipLaunchKernelGGL((k_elem_op<n, g>), grid, block, 0, s, m->d.elem_ops, m->d.nbr, x, y, cscale,        \
+                           (int32_t)m->E, nw, vbytes);                                                          \
+        return hipGetLastError();                                                                               \
+    }
+    STDG_NG(4, 1) STDG_NG(4, 2) STDG_NG(4, 3) STDG_NG(4, 4) STDG_NG(4, 5)
+    STDG_NG(10, 1) STDG_NG(10, 2) STDG_NG(10, 3) STDG_NG(10, 4) STDG_NG(10, 5)
+    STDG_NG(20, 1) STDG_NG(20, 2) STDG_NG(20, 3) STDG_NG(20, 4) STDG_NG(20, 5)
+#undef STDG_NG
+    return hipErrorInvalidValue;
 }
 
 hipError_t elem_iter_f32(const stdg_mesh* m, float* x, const float* r_in, const float* p_in, const float* q_in,

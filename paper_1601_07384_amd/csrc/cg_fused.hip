@@ -525,8 +525,10 @@ hipError_t op_n(const stdg_mesh* m, float* x, const float* r_in, const float* p_
         if (ITER) return lane_iter_f32(m, x, r_in, p_in, q_in, r_out, p_out, q_out, ab, cscale, precond, part_out, s);
         return lane_apply_f32(m, r_in, q_out, cscale, s);
     }
-    if (ITER && elem_supported(m))
-        return elem_iter_f32(m, x, r_in, p_in, q_in, r_out, p_out, q_out, ab, cscale, precond, part_out, s);
+    if (elem_supported(m)) {
+        if (ITER) return elem_iter_f32(m, x, r_in, p_in, q_in, r_out, p_out, q_out, ab, cscale, precond, part_out, s);
+        return elem_apply_f32(m, r_in, q_out, cscale, s);
+    }
     hipLaunchKernelGGL((k_cg_op<N, ITER>), dim3((unsigned)tile_blocks(m)), dim3(64 * WPB), 0, s, m->d.aop32, m->d.cls,
                        m->d.nbr, x, r_in, p_in, q_in, r_out, p_out, q_out, ab, cscale, precond, (int32_t)m->E,
                        (int32_t)m->G, g_multiplier(m), vbytes, part_out);

@@ -488,16 +488,20 @@ def test_block_jacobi_saves_iterations(n, p, pg, periodic):
 SQ3 = np.sqrt(3.0)
 
 
-@pytest.mark.parametrize("n,p,pg,periodic", [(4, 3, 1, True), (3, 2, 0, False), (3, 1, 1, False),
-                                             (5, 3, 0, False)])
-def test_spatial_apply_f32_matches_oracle(n, p, pg, periodic):
+@pytest.mark.parametrize("n,p,pg,periodic,jitter", [(4, 3, 1, True, 0.0), (3, 2, 0, False, 0.0),
+                                                     (3, 1, 1, False, 0.0), (5, 3, 0, False, 0.0),
+                                                     (3, 3, 1, False, 0.1), (3, 2, 1, True, 0.1)])
+def test_spatial_apply_f32_matches_oracle(n, p, pg, periodic, jitter):
     """(B (x) I) x = S (I (x) C^-1) x, with C = W T^-1 W from the hand-derived
     time matrices (W = I/2 and T of the p_gamma = 1 Gauss-Legendre basis; C = 1
-    for p_gamma = 0).  FP32 MFMA kernel against the FP64 oracle, 1e-5
-    relative; Dirichlet meshes give tiles that mix geometry classes."""
-    print(f"spatial f32 n={n} p={p} pg={pg} periodic={periodic}", flush=True)
-    X, T = case_mesh(n)
+    for p_gamma = 0).  FP32 kernels against the FP64 oracle, 1e-5 relative;
+    Dirichlet meshes give tiles that mix geometry classes, jittered ones run
+    the per-element operator (k_elem_op)."""
+    print(f"spatial f32 n={n} p={p} pg={pg} periodic={periodic} jitter={jitter}", flush=True)
+    X, T = case_mesh(n, jitter=jitter)
     m = P.Mesh(X, T, p, pg, dt=0.05, periodic=periodic)
+    if jitter:
+        assert m.inner_per_element
     ops = SpaceTimeOperators(OracleMesh(X, T, periodic=periodic), p, pg, 0.05)
     if pg == 0:
         Cinv = np.eye(1)
