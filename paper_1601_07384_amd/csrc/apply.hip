@@ -542,6 +542,8 @@ static hipError_t launch_apply(const stdg_mesh* m, const T* BT, const T* C, cons
     // the 82,944 / 24,576-element meshes), the direct-gather kernel elsewhere
     // and for FP32 everywhere.
     if constexpr (sizeof(T) == 8) {
+        // meshes whose elements carry their own blocks: the per-element FP64 tables
+        if (elem_apply64_supported(m)) return elem_apply_f64(m, C, x, y, s);
         // measured on MI355X (HIP events, median): 663,552-element p = 3 cube 174 (tn) -> 118 us
         // (two 16-element column groups per wavefront), 82,944-element p = 3, p_gamma = 1 cube
         // 92 (lds) -> 35 us; at p = 2 the MFMA kernel (32 us) only ties the run kernel

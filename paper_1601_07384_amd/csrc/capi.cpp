@@ -88,7 +88,7 @@ void free_tables(stdg_mesh* m) {
     for (void* p : {(void*)m->d.blocks, (void*)m->d.blocks32, (void*)m->d.aop32, (void*)m->d.cls, (void*)m->d.nbr,
                     (void*)m->d.C, (void*)m->d.C32, (void*)m->d.Cinv, (void*)m->d.Cinv32,
                     (void*)m->d.Cid, (void*)m->d.Cid32, (void*)m->d.chunk_slot, (void*)m->d.chunk_halo,
-                    (void*)m->d.lane_ops, (void*)m->d.elem_ops, (void*)m->d.run_cls, (void*)m->d.mixed_elems})
+                    (void*)m->d.lane_ops, (void*)m->d.elem_ops, (void*)m->d.elem_ops64, (void*)m->d.run_cls, (void*)m->d.mixed_elems})
         if (p) (void)hipFree(p);
     m->d = DeviceTables();
 }

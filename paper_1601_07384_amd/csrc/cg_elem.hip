@@ -355,6 +355,112 @@ __global__ void __launch_bounds__(64 * EWPB) k_elem_op(const float* __restrict__
     }
 }
 
+// y = S x in FP64 on per-element FP64 tables (the five operator blocks,
+// rows interleaved over the lanes like the FP32 table, two columns per
+// 16-byte load): lane q of an element forms rows q RPL .. of the five
+// products for every time node, then applies the G x G time factor C.
+// Table entry ((((R 5 + b) RPL + rr) NC2 + c2) 64 + l) 2 + j holds row
+// q RPL + rr, column 2 c2 + j of block b of element R EPW + l / L.
+template <int N, int G>
+__global__ void __launch_bounds__(64 * EWPB) k_elem_apply64(const double* __restrict__ table,
+                                                            const int32_t* __restrict__ nbr,
+                                                            const double* __restrict__ C, const double* x,
+                                                            double* __restrict__ y, int32_t E, uint32_t n_waves,
+                                                            uint32_t xbytes) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    typedef ElemShape<N> S;
+    constexpr int L = S::L, RPL = S::RPL, EPW = S::EPW, NC2 = (N + 1) / 2;
+    constexpr uint32_t ROWB = 8u * N;
+    constexpr size_t BSZ = (size_t)RPL * NC2 * 64;      // d2 entries of one block of a wavefront
+    const uint32_t lblock = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    const uint32_t wid = lblock * EWPB + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (wid >= n_waves) return;
+    const int lane = threadIdx.x & 63, q = lane % L, r0 = q * RPL;
+    const int32_t e = (int32_t)(wid * EPW) + lane / L;
+    const bool valid = e < E;
+    const Rsrc rn = make_rsrc(nbr, 16u * (uint32_t)E);
+    const i4v nb =
+        __builtin_bit_cast(i4v, __builtin_amdgcn_raw_buffer_load_b128(rn, (int)(valid ? 16u * e : OOB), 0, 0));
+    const Rsrc rx = make_rsrc(x, xbytes);
+    const d2* tb = (const d2*)table + (size_t)wid * 5 * BSZ + lane;
+    double acc[G][RPL];
+#pragma unroll
+    for (int a = 0; a < G; ++a)
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) acc[a][i] = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < 5; ++k) {
+        const int32_t src = k == 0 ? (valid ? e : -1) : (k == 1 ? nb.x : (k == 2 ? nb.y : (k == 3 ? nb.z : nb.w)));
+        const uint32_t off = src >= 0 ? (uint32_t)src * G * ROWB : OOB;
+        double v[G][N];
+#pragma unroll
+        for (int a = 0; a < G; ++a)
+#pragma unroll
+            for (int c2 = 0; c2 < N / 2; ++c2) {
+                const d2 t = __builtin_bit_cast(
+                    d2, __builtin_amdgcn_raw_buffer_load_b128(rx, (int)(off == OOB ? OOB : off + a * ROWB + 16u * c2),
+                                                              0, 0));
+                v[a][2 * c2] = t.x;
+                v[a][2 * c2 + 1] = t.y;
+            }
+        __builtin_amdgcn_sched_barrier(0);
+        const d2* tk = tb + (size_t)k * BSZ;
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+            d2 w[NC2];
+#pragma unroll
+            for (int c2 = 0; c2 < NC2; ++c2) w[c2] = __builtin_nontemporal_load(tk + 64 * (rr * NC2 + c2));
+#pragma unroll
+            for (int c2 = 0; c2 < NC2; ++c2)
+#pragma unroll
+                for (int a = 0; a < G; ++a) {
+                    acc[a][rr] = __builtin_fma(w[c2].x, v[a][2 * c2], acc[a][rr]);
+                    acc[a][rr] = __builtin_fma(w[c2].y, v[a][2 * c2 + 1], acc[a][rr]);
+                }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    if (!valid) return;
+    double Cm[G][G];
+#pragma unroll
+    for (int a = 0; a < G; ++a)
+#pragma unroll
+        for (int b = 0; b < G; ++b) Cm[a][b] = C[a * G + b];
+#pragma unroll
+    for (int a = 0; a < G; ++a)
+#pragma unroll
+        for (int i = 0; i < RPL; ++i)
+            if (r0 + i < N) {
+                double s = 0.0;
+#pragma unroll
+                for (int b = 0; b < G; ++b) s += Cm[a][b] * acc[b][i];
+                y[((int64_t)e * G + a) * N + r0 + i] = s;
+            }
+}
+
+template <int N> void elem_table64(const stdg_mesh* m, std::vector<double>& out) {
+    typedef ElemShape<N> S;
+    constexpr int L = S::L, RPL = S::RPL, EPW = S::EPW, NC2 = (N + 1) / 2;
+    const int64_t runs = (m->E + EPW - 1) / EPW;
+    out.assign((size_t)runs * 5 * RPL * NC2 * 64 * 2, 0.0);
+    for (int64_t e = 0; e < m->E; ++e) {
+        const int c = m->cls[e];
+        const int64_t R = e / EPW;
+        const int el = (int)(e % EPW);
+        for (int b = 0; b < 5; ++b) {
+            const double* M = m->blocks.data() + ((size_t)c * 5 + b) * N * N;
+            for (int qq = 0; qq < L; ++qq)
+                for (int rr = 0; rr < RPL; ++rr) {
+                    const int row = qq * RPL + rr;
+                    if (row >= N) continue;
+                    for (int col = 0; col < N; ++col)
+                        out[(((((size_t)R * 5 + b) * RPL + rr) * NC2 + col / 2) * 64 + el * L + qq) * 2 + col % 2] =
+                            M[row * N + col];
+                }
+        }
+    }
+}
+
 template <int N> void elem_table(const stdg_mesh* m, const std::vector<double>& inv, std::vector<float>& out) {
     typedef ElemShape<N> S;
     constexpr int L = S::L, RPL = S::RPL, EPW = S::EPW, NC4 = S::NC4;
@@ -415,7 +521,36 @@ int upload_elem_operands(stdg_mesh* m, const std::vector<double>& inv) {
     }
     STDG_HIP(hipMalloc(&m->d.elem_ops, t.size() * sizeof(float)));
     STDG_HIP(hipMemcpy(m->d.elem_ops, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+    if (8 * m->E * m->G * m->N < ((int64_t)1 << 31) && m->N % 2 == 0) {
+        std::vector<double> t64;
+        switch (m->N) {
+            case 4: elem_table64<4>(m, t64); break;
+            case 10: elem_table64<10>(m, t64); break;
+            default: elem_table64<20>(m, t64); break;
+        }
+        STDG_HIP(hipMalloc(&m->d.elem_ops64, t64.size() * sizeof(double)));
+        STDG_HIP(hipMemcpy(m->d.elem_ops64, t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     return STDG_OK;
+}
+
+bool elem_apply64_supported(const stdg_mesh* m) { return m->d.elem_ops64 != nullptr; }
+
+hipError_t elem_apply_f64(const stdg_mesh* m, const double* C, const double* x, double* y, hipStream_t s) {
+    const uint32_t xbytes = (uint32_t)(8 * m->E * m->G * m->N);
+    const dim3 grid((unsigned)elem_iter_blocks(m)), block(64 * EWPB);
+    const uint32_t nw = (uint32_t)elem_waves_n(m);
+#define STDG_NG(n, g)                                                                                            \
+    if (m->N == n && m->G == g) {                                                                                \
+        hipLaunchKernelGGL((k_elem_apply64<n, g>), grid, block, 0, s, m->d.elem_ops64, m->d.nbr, C, x, y,       \
+                           (int32_t)m->E, nw, xbytes);                                                           \
+        return hipGetLastError();                                                                                \
+    }
+    STDG_NG(4, 1) STDG_NG(4, 2) STDG_NG(4, 3) STDG_NG(4, 4) STDG_NG(4, 5)
+    STDG_NG(10, 1) STDG_NG(10, 2) STDG_NG(10, 3) STDG_NG(10, 4) STDG_NG(10, 5)
+    STDG_NG(20, 1) STDG_NG(20, 2) STDG_NG(20, 3) STDG_NG(20, 4) STDG_NG(20, 5)
+#undef STDG_NG
+    return hipErrorInvalidValue;
 }
 
 hipError_t elem_apply_f32(const stdg_mesh* m, const float* x, float* y, float cscale, hipStream_t s) {

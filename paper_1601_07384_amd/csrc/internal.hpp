@@ -42,6 +42,7 @@ struct DeviceTables {
     int chunk_hmax = 0;             // halo rows per chunk (multiple of 64)
     int64_t chunk_chunks = 0;
     float* elem_ops = nullptr;    // per-element FP32 blocks of the per-element PCG iteration (null: not used)
+    double* elem_ops64 = nullptr; // per-element FP64 operator blocks of the FP64 apply on such meshes
     float* lane_ops = nullptr;    // class operands of the element-per-lane kernels (null: a run mixes classes)
     int runs_uniform = 0;         // every 64-element run of the element order holds one class
     int32_t* run_cls = nullptr;   // [runs] class of a one-class 64-element run, -1 for a run of several

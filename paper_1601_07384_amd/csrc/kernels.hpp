@@ -32,6 +32,8 @@ hipError_t launch_cg_tail_f32(float* x, const float* p, int64_t n, const double*
 bool elem_supported(const stdg_mesh* m);
 int upload_elem_operands(stdg_mesh* m, const std::vector<double>& inv);
 int64_t elem_iter_blocks(const stdg_mesh* m);
+bool elem_apply64_supported(const stdg_mesh* m);
+hipError_t elem_apply_f64(const stdg_mesh* m, const double* C, const double* x, double* y, hipStream_t s);
 hipError_t elem_apply_f32(const stdg_mesh* m, const float* x, float* y, float cscale, hipStream_t s);
 hipError_t elem_iter_f32(const stdg_mesh* m, float* x, const float* r_in, const float* p_in, const float* q_in,
                          float* r_out, float* p_out, float* q_out, const double* ab, float cscale, int precond,
