@@ -702,6 +702,10 @@ int gmres(Ctx& c, const T* b, T* x, T* r, T* V, int mres, double tol_abs, int ma
 }
 
 template <typename T>
+int bicgstab(Ctx& c, const T* b, T* x, T* r, T* rh, T* p, T* v, T* s, T* t, double tol_abs, int max_it,
+             int check_every, int& iters, double& res_out);
+
+template <typename T>
 int run_krylov(Ctx& c, int method, const T* b, T* x, T* r, T* p, T* q, T* V, int mres, double tol_abs,
                int max_it, int check_every, int& iters, double& res) {
     if (method == STDG_CG) return cg<T>(c, b, x, r, p, q, tol_abs, max_it, check_every, iters, res);
