@@ -152,8 +152,10 @@ int stdg_mesh_build_host(const double* xyz, int64_t n_vert, const int64_t* tets,
  * stdg_dual_from_main, stdg_main_from_dual and stdg_divergence return
  * STDG_ERR_ARG.  When no element is curved the mesh is the straight one.
  * Errors: those of stdg_mesh_build; STDG_ERR_ARG for nodes == NULL;
- * STDG_ERR_MESH when vertex nodes differ from xyz (relative 1e-12) or two
- * elements do not share a curved face (relative 1e-9). */
+ * STDG_ERR_MESH when vertex nodes differ from xyz (relative 1e-12), two
+ * elements do not share a curved face (relative 1e-9), or an element's map
+ * folds (det J at a quadrature point of opposite sign to, or below 1e-12
+ * times, its value at the element's barycentre). */
 int stdg_mesh_build_curved(const double* xyz, int64_t n_vert, const int64_t* tets,
                            int64_t n_tet, const double* nodes, int32_t host_only,
                            const stdg_config* cfg, stdg_mesh** out);

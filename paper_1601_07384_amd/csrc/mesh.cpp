@@ -210,7 +210,9 @@ static real inv3(const real J[9], real Ji[9]) {
 // and of its neighbour across t's local face f (Xk translated by shk next to
 // t); kv[i] the neighbour's local vertex at t's i-th face vertex (face
 // vertices = t's local vertices other than f, ascending).  Returns -2 when the
-// two elements do not share the curved face.
+// two elements do not share the curved face, -3 when the map of either
+// element folds (det J at a quadrature point of its sub-tetrahedron has the
+// opposite sign of det J at the element's barycentre, or vanishes).
 static int curved_face_blocks(const NodalBasis& phi, int p, const V3* Xt, int f, const V3* Xk, const V3& shk,
                               const int kv[3], DualFaceBlocks& out) {
     const int N = phi.N;
@@ -255,10 +257,15 @@ static int curved_face_blocks(const NodalBasis& phi, int p, const V3* Xt, int f,
     for (int s = 0; s < 2; ++s) {
         const Affine sa(std::array<V3, 4>{bref, ref[s][0], ref[s][1], ref[s][2]});
         const real jsub = std::fabs(sa.det);
+        V3 xb;
+        map(s, bref, xb);
+        const real det_b = inv3(J, Ji);                          // orientation of the element
         for (size_t q = 0; q < tr.w.size(); ++q) {
             V3 x;
             map(s, sa.to_phys(tr.pts[q]), x);
-            const real w = tr.w[q] * jsub * std::fabs(inv3(J, Ji));
+            const real dj = inv3(J, Ji);
+            if (!(dj * det_b > 1e-12L * det_b * det_b)) return -3;
+            const real w = tr.w[q] * jsub * std::fabs(dj);
             taylor_eval(ex, x, x0, h, ps.data());
             for (int k = 0; k < N; ++k)          // J^-T grad_xi
                 for (int d = 0; d < 3; ++d)
@@ -335,8 +342,8 @@ static int element_blocks(const stdg_mesh* m, int64_t t, const NodalBasis& phi, 
                     if (norm(sub(Vk[b], m->vert[t][a])) < norm(sub(Vk[best], m->vert[t][a]))) best = b;
                 kv[n++] = best;
             }
-            if (curved_face_blocks(phi, m->p, m->geo.data() + t * N, f, m->geo.data() + k * N, sh, kv, fb) != 0)
-                return -2;
+            const int r = curved_face_blocks(phi, m->p, m->geo.data() + t * N, f, m->geo.data() + k * N, sh, kv, fb);
+            if (r != 0) return r;
         } else {
             dual_face_blocks(phi, m->p, m->vert[t], f, Vk, fb);
         }
@@ -675,14 +682,16 @@ int build_blocks(stdg_mesh* m, const std::vector<int64_t>& rep) {
     const int N = m->N;
     m->blocks.assign((size_t)m->n_classes * 5 * N * N, 0.0);
     const NodalBasis phi(m->p);
-    int bad = 0, open = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad, open)
+    int bad = 0, open = 0, fold = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad, open, fold)
     for (int c = 0; c < m->n_classes; ++c) {
         const int r = element_blocks(m, rep[c], phi, m->blocks.data() + (size_t)c * 5 * N * N);
         bad += r == -1;
         open += r == -2;
+        fold += r == -3;
     }
     if (open) { set_error("curved elements do not share their common face (non-conforming nodes)"); return STDG_ERR_MESH; }
+    if (fold) { set_error("curved element folds (det J changes sign inside it)"); return STDG_ERR_MESH; }
     if (bad) { set_error("dual mass matrix not positive definite (degenerate dual element)"); return STDG_ERR_MESH; }
     time_factor(m->G, m->Ctime);
     return STDG_OK;

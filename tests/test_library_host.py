@@ -204,3 +204,14 @@ def test_curved_mesh_errors():
         P.Mesh(Xc, T, 2, 0, device=False, nodes=bad)
     with pytest.raises(ValueError):
         P.Mesh(Xc, T, 2, 0, device=False, nodes=nodes[:, :5])
+    # an interior edge node pushed through the element (the same for every
+    # element sharing the edge): the map folds
+    from stdg_inputs import node_coordinates
+    X3, T3 = kuhn_mesh(3)
+    n3 = node_coordinates(X3, T3, 2)
+    centre = np.array([0.5, 0.5, 0.5])
+    moved = np.abs(n3 - centre).max(axis=-1) < 1e-12
+    assert moved.any()
+    n3[moved] += np.array([0.3, 0.3, -0.3])
+    with pytest.raises(RuntimeError, match="folds"):
+        P.Mesh(X3, T3, 2, 0, device=False, nodes=n3)
