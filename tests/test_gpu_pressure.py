@@ -117,7 +117,7 @@ def test_apply_c5_full_size_sampled_rows():
     assert _sampled_rows(32, 2, 1, True, 1e-3, 24, 8) <= 1e-12
 
 
-@pytest.mark.parametrize("n,p,pg", [(8, 4, 2), (8, 3, 1), (16, 3, 1)])
+@pytest.mark.parametrize("n,p,pg", [(8, 4, 2), (8, 3, 1), (16, 3, 1), (8, 3, 0), (8, 4, 0)])
 def test_apply_dirichlet_mixed_runs_sampled_rows(n, p, pg):
     """Dirichlet cubes: most 64-element runs hold one class (FP64 matrix-core
     kernel), the boundary-class tails several (the list kernel); sampled rows
