@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <unordered_map>
 
@@ -191,6 +192,57 @@ static void iso_point(const NodalBasis& phi, const V3* X, const V3& xi, real* va
         }
 }
 
+// x and J of the map with nodes X from the basis values and gradients at a point
+static void iso_from(int N, const V3* X, const real* val, const real* grad, V3& x, real J[9]) {
+    x = {0, 0, 0};
+    for (int i = 0; i < 9; ++i) J[i] = 0;
+    for (int k = 0; k < N; ++k)
+        for (int r = 0; r < 3; ++r) {
+            x[r] += X[k][r] * val[k];
+            for (int c = 0; c < 3; ++c) J[r * 3 + c] += X[k][r] * grad[3 * k + c];
+        }
+}
+
+// The volume rule of the reference sub-tetrahedron of local face g (the
+// reference barycentre and the face's vertices in ascending order), with the
+// nodal basis and its reference gradients at its points: the same for every
+// curved element, so built once per degree and face.
+struct SubTetRule {
+    std::vector<V3> xi;
+    std::vector<real> w, val, grad;   // w includes the sub-tetrahedron's volume factor
+};
+static const SubTetRule& subtet_rule(const NodalBasis& phi, int g) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, SubTetRule> cache;
+    const std::pair<int, int> key(phi.p, g);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        const auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const int p = phi.p, N = phi.N;
+    const Rule& tr = tet_rule(p * p + (3 * p - 1) / 2);      // exact for degree 2p^2 + 3p - 3
+    std::array<V3, 4> sv;
+    sv[0] = {0.25L, 0.25L, 0.25L};
+    for (int k = 0, n = 1; k < 4; ++k)
+        if (k != g) sv[n++] = kRefVert[k];
+    const Affine sa(sv);
+    SubTetRule r;
+    const size_t nq = tr.w.size();
+    r.xi.resize(nq);
+    r.w.resize(nq);
+    r.val.resize(nq * N);
+    r.grad.resize(nq * 3 * N);
+    for (size_t q = 0; q < nq; ++q) {
+        r.xi[q] = sa.to_phys(tr.pts[q]);
+        r.w[q] = tr.w[q] * std::fabs(sa.det);
+        phi.eval(r.xi[q], r.val.data() + q * N);
+        phi.grad(r.xi[q], r.grad.data() + q * 3 * N);
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    return cache.emplace(key, std::move(r)).first->second;    // map entries never move
+}
+
 static real inv3(const real J[9], real Ji[9]) {
     const real det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
                      J[2] * (J[3] * J[7] - J[4] * J[6]);
@@ -253,24 +305,25 @@ static int curved_face_blocks(const NodalBasis& phi, int p, const V3* Xt, int f,
 
     out.M.assign(N * N, 0.0);
     for (int s = 0; s < 2; ++s) out.Q[s].assign(3 * N * N, 0.0);
-    const Rule& tr = tet_rule(p * p + (3 * p - 1) / 2);      // exact for degree 2p^2 + 3p - 3
+    const int gk = 6 - kv[0] - kv[1] - kv[2];                  // the neighbour's local face
     for (int s = 0; s < 2; ++s) {
-        const Affine sa(std::array<V3, 4>{bref, ref[s][0], ref[s][1], ref[s][2]});
-        const real jsub = std::fabs(sa.det);
+        const SubTetRule& tr = subtet_rule(phi, s == 0 ? f : gk);
         V3 xb;
         map(s, bref, xb);
         const real det_b = inv3(J, Ji);                          // orientation of the element
         for (size_t q = 0; q < tr.w.size(); ++q) {
             V3 x;
-            map(s, sa.to_phys(tr.pts[q]), x);
+            const real* gq = tr.grad.data() + q * 3 * N;
+            iso_from(N, X[s], tr.val.data() + q * N, gq, x, J);
+            x = add(x, sh[s]);
             const real dj = inv3(J, Ji);
             if (!(dj * det_b > 1e-12L * det_b * det_b)) return -3;
-            const real w = tr.w[q] * jsub * std::fabs(dj);
+            const real w = tr.w[q] * std::fabs(dj);
             taylor_eval(ex, x, x0, h, ps.data());
             for (int k = 0; k < N; ++k)          // J^-T grad_xi
                 for (int d = 0; d < 3; ++d)
-                    gx[3 * k + d] = Ji[0 * 3 + d] * grad[3 * k + 0] + Ji[1 * 3 + d] * grad[3 * k + 1] +
-                                    Ji[2 * 3 + d] * grad[3 * k + 2];
+                    gx[3 * k + d] = Ji[0 * 3 + d] * gq[3 * k + 0] + Ji[1 * 3 + d] * gq[3 * k + 1] +
+                                    Ji[2 * 3 + d] * gq[3 * k + 2];
             for (int a = 0; a < N; ++a) {
                 const real wa = w * ps[a];
                 for (int b = 0; b < N; ++b) out.M[a * N + b] += wa * ps[b];
